@@ -1,0 +1,51 @@
+"""Write the stored trajectory fixtures under tests/golden/ from the CPU oracle alone.
+
+Run from the repository root:  python tests/golden/make_golden.py
+It imports only the oracle and the seeded input generator.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import loopgen  # noqa: E402
+from oracle import ks_loop as K  # noqa: E402
+
+
+def band_list(u, Nx, Ns):
+    Kx, Ks = K.band_limits(Nx, Ns)
+    out = []
+    for j in range(Kx + 1):
+        for k in range(-Ks, Ks + 1):
+            v = u[k % Ns, j]
+            out.append([j, k, float(v.real), float(v.imag)])
+    return out
+
+
+def trajectory(c, steps, scheme, dtau, marks):
+    spec = loopgen.config_loops(c)[0]
+    u, T, Jh = K.step(spec.uhat, spec.T, spec.L, dtau, scheme, steps)
+    return {
+        "workload": loopgen.CONFIGS[c]["name"], "seed": spec.seed, "L": spec.L, "Nx": spec.Nx,
+        "Ns": spec.Ns, "T0": spec.T, "dtau": dtau, "scheme": "imex" if scheme == K.IMEX else "explicit",
+        "steps": steps, "J_hist_marks": {str(m): float(Jh[m]) for m in marks},
+        "T_final": float(T), "uhat_final_band": band_list(u, spec.Nx, spec.Ns),
+    }
+
+
+def main():
+    data = trajectory(1, 2000, K.EXPLICIT, 1e-4, [0, 1, 10, 100, 1000, 1999])
+    with open(os.path.join(HERE, "oracle_traj_plain32x32.json"), "w") as f:
+        json.dump(data, f, indent=1)
+    data = trajectory(2, 200, K.IMEX, 5e-5, [0, 1, 10, 100, 199])
+    data.pop("uhat_final_band")
+    with open(os.path.join(HERE, "oracle_traj_plain64x128_200.json"), "w") as f:
+        json.dump(data, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
