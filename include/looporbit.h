@@ -1,0 +1,115 @@
+/* looporbit.h - C ABI of the MI355X (gfx950) library for one fictitious-time step of the
+ * Kuramoto-Sivashinsky loop dynamics of the adjoint-based variational method
+ * (Azimi, Ashtari & Schneider, arXiv:2007.06427).
+ *
+ * A loop l = [u(x, s); T] is a real field on x in [0, L), s in [0, 1), periodic in both, plus
+ * its period T > 0 (Sec. 2, eq. loop_def). Its field is represented by Fourier coefficients
+ * on an Nx x Ns grid (Sec. 4.2, eq. 2D_Fourier), truncated by the two-thirds rule in both
+ * directions: |j| <= Kx = (Nx-1)/3 and |k| <= Ks = (Ns-1)/3, with integer division.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers are DEVICE pointers owned by the caller. Complex arrays are interleaved
+ *   (re, im) doubles and must be 16-byte aligned; double arrays must be 8-byte aligned.
+ * - Spectral layout ("rfft layout"): one loop occupies Ns * (Nx/2 + 1) complex values.
+ *   Element [k][j] (row-major) holds u_hat_{j,k} for j = 0 .. Nx/2, with row k holding
+ *   temporal mode k in FFT order (k < Ns/2 are the non-negative modes, k >= Ns/2 stand for
+ *   k - Ns). This is the layout of a forward-normalised real-to-complex 2D transform of the
+ *   real (Ns, Nx) grid. A batch of nloops loops of one shape is stored back to back.
+ * - Inputs: entries outside the band are ignored. Column j = 0 is read through its
+ *   Hermitian part (u_{0,k} + conj(u_{0,-k})) / 2, the column a real-valued inverse
+ *   transform uses.
+ * - Outputs: every entry of an output array is written, and entries outside the band are 0.
+ * - J is HALF the paper's cost: J = 1/2 int_0^1 int_0^L r^2 dx ds. Then the paper's flow
+ *   (eq. KS_G) is exactly G = -grad J in the inner product of eq. inner_product_definition.
+ * - Results go to device memory and work is queued on `stream` (a hipStream_t, or NULL for
+ *   the default stream). No call synchronises with the host, allocates, or frees memory,
+ *   except that the first call on a device creates that device's twiddle table, and
+ *   loop_status_sync waits for the stream. Every call may therefore be recorded into a HIP
+ *   graph once the device is initialised (loop_init).
+ * - Work space: `ws` is a caller-owned device buffer of at least loop_workspace_bytes(...)
+ *   bytes, prepared once by loop_workspace_init. One work space per concurrently running
+ *   stream. Calls that share a work space must be ordered on one stream.
+ * - Errors: every call returns a loop_status. Argument checks run on the host before any
+ *   work is queued. Nothing is queued when a check fails. Conditions that only the device
+ *   can see (a non-finite or non-positive period, a non-finite cost) set a sticky status
+ *   word in the work space, and loop_status_sync returns it.
+ * - Sizes: Nx and Ns must be powers of two in [8, 1024]; 1 <= nloops <= 1<<20.
+ */
+#ifndef LOOPORBIT_H
+#define LOOPORBIT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LOOP_OK = 0,
+    LOOP_EINVAL = -1,      /* bad size, pointer, alignment, L, dtau or scheme */
+    LOOP_ENOTSUP = -2,     /* a size the library does not support (e.g. Nx not a power of two) */
+    LOOP_EHIP = -3,        /* a HIP runtime call failed */
+    LOOP_ENONFINITE = -4,  /* device saw T <= 0 or a non-finite T or J (sticky, see loop_status_sync) */
+    LOOP_EWORKSPACE = -5,  /* work space too small or not prepared by loop_workspace_init */
+    LOOP_EHANG = -6        /* the batched scheduler's bounded dependency wait ran out (sticky) */
+} loop_status;
+
+typedef enum { LOOP_EULER_EXPLICIT = 0, LOOP_EULER_IMEX = 1 } loop_scheme;
+
+/* Create this device's twiddle table (long-double accurate e^{-2 pi i t / 4096}). The current
+ * HIP device is used. Calling it again is harmless. Must not be called under stream capture. */
+int loop_init(void);
+
+/* Release the tables of every device. */
+int loop_shutdown(void);
+
+/* Bytes of work space needed by a uniform batch of nloops loops of shape (Nx, Ns). */
+int loop_workspace_bytes(int Nx, int Ns, int nloops, size_t* bytes);
+
+/* Clear the status word and stamp the work space as prepared. Call once after allocating. */
+int loop_workspace_init(void* ws, size_t ws_bytes, void* stream);
+
+/* Residual r = -(1/T) u_s - u u_x - u_xx - u_xxxx (eq. KS_R), truncated to the band.
+ * T[nloops] periods; uhat, rhat: nloops spectra in rfft layout. rhat must not alias uhat. */
+int loop_residual(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat,
+                  double* rhat, void* ws, size_t ws_bytes, void* stream);
+
+/* Cost J = 1/2 int int r^2 dx ds (half of eq. cost_function), one per loop into J[nloops]. */
+int loop_cost(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat,
+              double* J, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint gradient (eq. KS_G, App. B):
+ *   Ghat = G_1 = -(1/T) r_s - u r_x + r_xx + r_xxxx (band, rfft layout),
+ *   dJdT[l] = int int (1/T^2) u_s r dx ds = -G_2,   J[l] as in loop_cost.
+ * Any of dJdT, J may be NULL. Ghat must not alias uhat. */
+int loop_adjoint_grad(double L, int Nx, int Ns, int nloops, const double* T,
+                      const double* uhat, double* Ghat, double* dJdT, double* J,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* nsteps fictitious-time steps in place (Sec. 4.2):
+ *   EXPLICIT: u_hat <- u_hat + dtau * G_1
+ *   IMEX:     u_hat <- u_hat + dtau * G_1 / (1 - dtau * lambda_{j,k}(T)), the semi-implicit Euler
+ *             step with the linear part lambda = -(2 pi k/T)^2 - q^8 + 2 q^6 - q^4 implicit
+ *   T <- T - dtau * dJ/dT (explicit Euler), both from the state at the start of the step.
+ * uhat is first made canonical in place (band-limited, real column 0). J_hist, if not NULL,
+ * receives J at the start of every step as J_hist[step * nloops + l]. */
+int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau,
+              int scheme, int nsteps, double* J_hist, void* ws, size_t ws_bytes, void* stream);
+
+/* The update half of loop_step, for a G_1 computed elsewhere (e.g. by autograd):
+ * uhat <- canonical(uhat) + dtau * sigma * Ghat (band), T <- T - dtau * dJdT[l]. */
+int loop_update(double L, int Nx, int Ns, int nloops, double* T, double* uhat,
+                const double* Ghat, const double* dJdT, double dtau, int scheme, void* stream);
+
+/* Read (and clear) the sticky device status of a work space. Waits for `stream`. */
+int loop_status_sync(void* ws, void* stream);
+
+/* Human-readable text for a loop_status value. */
+const char* loop_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOOPORBIT_H */

@@ -1,0 +1,80 @@
+"""ctypes binding of liblooporbit.so: the C-ABI entry points under their own names.
+
+Functions here marshal arguments only (tensors to device pointers, the current stream) and
+raise LoopOrbitError on a non-zero status. All arithmetic runs in the HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblooporbit.so")
+
+LOOP_OK = 0
+LOOP_EINVAL = -1
+LOOP_ENOTSUP = -2
+LOOP_EHIP = -3
+LOOP_ENONFINITE = -4
+LOOP_EWORKSPACE = -5
+LOOP_EHANG = -6
+EXPLICIT = 0
+IMEX = 1
+
+# every symbol include/looporbit.h declares
+EXPORTS = [
+    "loop_init", "loop_shutdown", "loop_workspace_bytes", "loop_workspace_init", "loop_residual",
+    "loop_cost", "loop_adjoint_grad", "loop_step", "loop_update", "loop_status_sync", "loop_status_string",
+]
+
+
+class LoopOrbitError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+_lib = None
+
+_d = ctypes.c_double
+_i = ctypes.c_int
+_p = ctypes.c_void_p
+_sz = ctypes.c_size_t
+
+_SIGS = {
+    "loop_init": ([], _i),
+    "loop_shutdown": ([], _i),
+    "loop_workspace_bytes": ([_i, _i, _i, ctypes.POINTER(_sz)], _i),
+    "loop_workspace_init": ([_p, _sz, _p], _i),
+    "loop_residual": ([_d, _i, _i, _i, _p, _p, _p, _p, _sz, _p], _i),
+    "loop_cost": ([_d, _i, _i, _i, _p, _p, _p, _p, _sz, _p], _i),
+    "loop_adjoint_grad": ([_d, _i, _i, _i, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
+    "loop_step": ([_d, _i, _i, _i, _p, _p, _d, _i, _i, _p, _p, _sz, _p], _i),
+    "loop_update": ([_d, _i, _i, _i, _p, _p, _p, _p, _d, _i, _p], _i),
+    "loop_status_sync": ([_p, _p], _i),
+    "loop_status_string": ([_i], ctypes.c_char_p),
+}
+
+
+def lib():
+    """Load liblooporbit.so (built in-tree). Raises if it is missing: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2007_06427_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().loop_status_string(int(status)).decode()
+
+
+def check(status: int, where: str) -> None:
+    if status != LOOP_OK:
+        raise LoopOrbitError(status, where)

@@ -1,0 +1,149 @@
+"""Tensor-level binding of the C ABI. Every function takes device tensors and queues work
+on the current torch stream.
+
+Shapes: uhat is complex128 of shape (nloops, Ns, Nx//2 + 1) or (Ns, Nx//2 + 1), in the rfft
+layout of include/looporbit.h. T is float64 of shape (nloops,). Torch provides device memory
+and streams only. All arithmetic runs in liblooporbit.so.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import EXPLICIT, IMEX, LoopOrbitError, check  # noqa: F401
+
+_WS: Dict[Tuple[int, int], "Workspace"] = {}
+
+
+def _stream_ptr(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def shape_of(uhat: torch.Tensor):
+    """(nloops, Nx, Ns) of an rfft-layout tensor, which must be a contiguous complex128 CUDA tensor."""
+    if uhat.dtype != torch.complex128:
+        raise TypeError("uhat must be complex128")
+    if not uhat.is_cuda:
+        raise ValueError("uhat must be a device tensor")
+    if not uhat.is_contiguous():
+        raise ValueError("uhat must be contiguous")
+    if uhat.dim() == 2:
+        nl, Ns, H = 1, uhat.shape[0], uhat.shape[1]
+    elif uhat.dim() == 3:
+        nl, Ns, H = uhat.shape
+    else:
+        raise ValueError("uhat must be (Ns, Nx//2+1) or (nloops, Ns, Nx//2+1)")
+    return int(nl), 2 * (int(H) - 1), int(Ns)
+
+
+def _periods(T, nl, device):
+    if not isinstance(T, torch.Tensor):
+        T = torch.full((nl,), float(T), dtype=torch.float64, device=device)
+    if T.dtype != torch.float64 or not T.is_cuda or not T.is_contiguous() or T.numel() != nl:
+        raise ValueError("T must be a contiguous float64 device tensor with one entry per loop")
+    return T
+
+
+def workspace_bytes(Nx: int, Ns: int, nloops: int) -> int:
+    n = ctypes.c_size_t(0)
+    check(_lib.lib().loop_workspace_bytes(Nx, Ns, nloops, ctypes.byref(n)), "loop_workspace_bytes")
+    return int(n.value)
+
+
+class Workspace:
+    """A device work space (caller-owned memory of the C ABI), prepared by loop_workspace_init."""
+
+    def __init__(self, nbytes: int, device=None):
+        device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        self.nbytes = int(self.buf.numel())
+        check(_lib.lib().loop_workspace_init(_ptr(self.buf), self.nbytes, _stream_ptr()), "loop_workspace_init")
+
+    @property
+    def ptr(self):
+        return _ptr(self.buf)
+
+    def status(self) -> int:
+        """Read and clear the sticky device status (synchronises the current stream)."""
+        return int(_lib.lib().loop_status_sync(self.ptr, _stream_ptr()))
+
+
+def workspace(Nx: int, Ns: int, nloops: int, device=None) -> Workspace:
+    """A cached work space big enough for (Nx, Ns, nloops) on the current device."""
+    need = workspace_bytes(Nx, Ns, nloops)
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index
+    key = (dev, 0)
+    ws = _WS.get(key)
+    if ws is None or ws.nbytes < need:
+        ws = Workspace(need, device=torch.device("cuda", dev))
+        _WS[key] = ws
+    return ws
+
+
+def init() -> None:
+    check(_lib.lib().loop_init(), "loop_init")
+
+
+def loop_residual(uhat: torch.Tensor, T, L: float, out: torch.Tensor = None, ws: Workspace = None) -> torch.Tensor:
+    nl, Nx, Ns = shape_of(uhat)
+    T = _periods(T, nl, uhat.device)
+    out = torch.empty_like(uhat) if out is None else out
+    ws = ws or workspace(Nx, Ns, nl)
+    check(_lib.lib().loop_residual(float(L), Nx, Ns, nl, _ptr(T), _ptr(uhat), _ptr(out), ws.ptr, ws.nbytes,
+                                   _stream_ptr()), "loop_residual")
+    return out
+
+
+def loop_cost(uhat: torch.Tensor, T, L: float, out: torch.Tensor = None, ws: Workspace = None) -> torch.Tensor:
+    nl, Nx, Ns = shape_of(uhat)
+    T = _periods(T, nl, uhat.device)
+    out = torch.empty(nl, dtype=torch.float64, device=uhat.device) if out is None else out
+    ws = ws or workspace(Nx, Ns, nl)
+    check(_lib.lib().loop_cost(float(L), Nx, Ns, nl, _ptr(T), _ptr(uhat), _ptr(out), ws.ptr, ws.nbytes,
+                               _stream_ptr()), "loop_cost")
+    return out
+
+
+def loop_adjoint_grad(uhat: torch.Tensor, T, L: float, ws: Workspace = None):
+    """Returns (G1_hat, dJ/dT, J): the flow's field component, the period derivative and the cost."""
+    nl, Nx, Ns = shape_of(uhat)
+    T = _periods(T, nl, uhat.device)
+    G = torch.empty_like(uhat)
+    dJdT = torch.empty(nl, dtype=torch.float64, device=uhat.device)
+    J = torch.empty(nl, dtype=torch.float64, device=uhat.device)
+    ws = ws or workspace(Nx, Ns, nl)
+    check(_lib.lib().loop_adjoint_grad(float(L), Nx, Ns, nl, _ptr(T), _ptr(uhat), _ptr(G), _ptr(dJdT), _ptr(J),
+                                       ws.ptr, ws.nbytes, _stream_ptr()), "loop_adjoint_grad")
+    return G, dJdT, J
+
+
+def loop_step(uhat: torch.Tensor, T: torch.Tensor, L: float, dtau: float, scheme: int = EXPLICIT,
+              nsteps: int = 1, J_hist: torch.Tensor = None, ws: Workspace = None):
+    """Advance (uhat, T) in place by nsteps. J_hist, if given, is float64 (nsteps, nloops)."""
+    nl, Nx, Ns = shape_of(uhat)
+    T = _periods(T, nl, uhat.device)
+    if J_hist is not None and (J_hist.dtype != torch.float64 or J_hist.numel() < nsteps * nl
+                               or not J_hist.is_contiguous()):
+        raise ValueError("J_hist must be a contiguous float64 tensor with nsteps * nloops entries")
+    ws = ws or workspace(Nx, Ns, nl)
+    jh = _ptr(J_hist) if J_hist is not None else None
+    check(_lib.lib().loop_step(float(L), Nx, Ns, nl, _ptr(T), _ptr(uhat), float(dtau), int(scheme), int(nsteps),
+                               jh, ws.ptr, ws.nbytes, _stream_ptr()), "loop_step")
+    return uhat, T
+
+
+def loop_update(uhat: torch.Tensor, T: torch.Tensor, L: float, Ghat: torch.Tensor, dJdT: torch.Tensor,
+                dtau: float, scheme: int = EXPLICIT):
+    nl, Nx, Ns = shape_of(uhat)
+    T = _periods(T, nl, uhat.device)
+    check(_lib.lib().loop_update(float(L), Nx, Ns, nl, _ptr(T), _ptr(uhat), _ptr(Ghat), _ptr(dJdT), float(dtau),
+                                 int(scheme), _stream_ptr()), "loop_update")
+    return uhat, T

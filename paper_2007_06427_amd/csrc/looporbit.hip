@@ -1,0 +1,500 @@
+// liblooporbit: C ABI and kernels for the fictitious-time step of the KS loop dynamics
+// (Azimi, Ashtari & Schneider, arXiv:2007.06427, Sec. 3-4). See include/looporbit.h for the
+// contract of each entry point and passes.hpp for the pass decomposition.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "looporbit.h"
+#include "passes.hpp"
+
+using namespace lo;
+
+namespace {
+
+// ============================================================================ kernels
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_colA(Shape sh, const cd* __restrict__ uhat, Work w,
+                                                 const cd* __restrict__ tw) {
+    __shared__ cd ex[2048];
+    col_pass_A<N>(sh, blockIdx.x, uhat, w, ex, tw);
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_rowB(Shape sh, Work w, const cd* __restrict__ tw) {
+    __shared__ cd tile[RowGeom<M>::ROWS * RowGeom<M>::CMAX];
+    __shared__ cd ex[2048];
+    row_pass_B<M>(sh, blockIdx.x, w, tile, ex, tw);
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_colC(Shape sh, const cd* __restrict__ uhat,
+                                                 const double* __restrict__ T, Work w, cd* rhat_out, int mode,
+                                                 const cd* __restrict__ tw) {
+    __shared__ cd ex[2048];
+    col_pass_C<N>(sh, blockIdx.x, uhat, T, w, rhat_out, mode, ex, tw);
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_rowD(Shape sh, Work w, double* T, int mode, double dtau,
+                                                 double* J_hist, double* Jout, double* dJdTout,
+                                                 const cd* __restrict__ tw) {
+    __shared__ cd tile[2 * RowGeom<M>::ROWS * RowGeom<M>::CMAX];
+    __shared__ cd ex[2048];
+    row_pass_D<M>(sh, blockIdx.x, w, T, mode, dtau, J_hist, Jout, dJdTout, tile, ex, tw);
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_colE(Shape sh, cd* uhat, Work w, cd* Gout, int mode, double dtau,
+                                                 int scheme, const cd* __restrict__ tw) {
+    __shared__ cd ex[2048];
+    col_pass_E<N>(sh, blockIdx.x, uhat, w, Gout, mode, dtau, scheme, ex, tw);
+}
+
+__global__ void k_finalize(Shape sh, Work w, double* T, double* Jout, double* dJdTout) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < sh.nloops) finalize_loop(sh, l, w, T, MODE_COST, 0.0, nullptr, Jout, dJdTout);
+}
+
+// Make a state canonical in place: band-limited, column 0 Hermitian.
+__global__ void k_canonicalize(Shape sh, cd* uhat) {
+    const size_t per = (size_t)sh.N * sh.H;
+    const size_t total = per * sh.nloops;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t l = i / per;
+        const int e = (int)((i % per) / sh.H), j = (int)(i % sh.H);
+        cd* u = uhat + l * per;
+        const bool inb = band_row(e, sh.N, sh.Ks) >= 0 && j < sh.C;
+        if (j > 0) {
+            if (!inb) u[(size_t)e * sh.H + j] = cd{0.0, 0.0};
+        } else if (e <= sh.N / 2) {
+            const int e2 = (sh.N - e) & (sh.N - 1);
+            if (inb) {
+                const cd a = u[(size_t)e * sh.H], b = u[(size_t)e2 * sh.H];
+                const cd v{0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
+                u[(size_t)e * sh.H] = v;
+                u[(size_t)e2 * sh.H] = cconj(v);
+            } else {
+                u[(size_t)e * sh.H] = cd{0.0, 0.0};
+                u[(size_t)e2 * sh.H] = cd{0.0, 0.0};
+            }
+        }
+    }
+}
+
+// Zero columns j >= C of an rfft-layout output.
+__global__ void k_zero_outer_cols(Shape sh, cd* out) {
+    const int W = sh.H - sh.C;
+    const size_t total = (size_t)sh.nloops * sh.N * W;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t row = i / W;
+        const int j = sh.C + (int)(i % W);
+        out[row * sh.H + j] = cd{0.0, 0.0};
+    }
+}
+
+// uhat <- canonical(uhat) + dtau * sigma * Hermitian-part(Ghat) in the band, 0 outside.
+__global__ void k_update(Shape sh, const double* __restrict__ T, cd* uhat, const cd* __restrict__ Ghat,
+                         double dtau, int scheme) {
+    const size_t per = (size_t)sh.N * sh.H;
+    const size_t total = per * sh.nloops;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t l = i / per;
+        const int e = (int)((i % per) / sh.H), j = (int)(i % sh.H);
+        if (j == 0 && e > sh.N / 2) continue;  // handled with its partner row
+        cd* u = uhat + l * per;
+        const cd* g = Ghat + l * per;
+        const bool inb = band_row(e, sh.N, sh.Ks) >= 0 && j < sh.C;
+        if (!inb) {
+            u[(size_t)e * sh.H + j] = cd{0.0, 0.0};
+            if (j == 0) u[(size_t)((sh.N - e) & (sh.N - 1)) * sh.H] = cd{0.0, 0.0};
+            continue;
+        }
+        const cd uu = load_state(u, e, j, sh.N, sh.H);
+        const cd gg = load_state(g, e, j, sh.N, sh.H);
+        double sig = 1.0;
+        if (scheme == 1) {
+            const int k = (e < sh.N / 2) ? e : e - sh.N;
+            const double q = kTwoPi * j / sh.L, q2 = q * q, q4 = q2 * q2;
+            const double a = kTwoPi * k / T[l];
+            sig = 1.0 / (1.0 - dtau * (-a * a - q4 * q4 + 2.0 * q4 * q2 - q4));
+        }
+        const double s = dtau * sig;
+        const cd v{uu.x + s * gg.x, uu.y + s * gg.y};
+        u[(size_t)e * sh.H + j] = v;
+        if (j == 0) u[(size_t)((sh.N - e) & (sh.N - 1)) * sh.H] = cconj(v);
+    }
+}
+
+__global__ void k_update_T(int nloops, double* T, const double* __restrict__ dJdT, double dtau) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < nloops) T[l] = T[l] - dtau * dJdT[l];
+}
+
+constexpr uint64_t kWsMagic = 0x4c4f4f504f524254ull;  // "LOOPORBT"
+
+struct WsHeader {
+    int status;
+    int pad;
+    uint64_t magic;
+};
+
+__global__ void k_ws_init(WsHeader* h) {
+    h->status = 0;
+    h->magic = kWsMagic;
+}
+
+__global__ void k_ws_clear_status(WsHeader* h) { h->status = 0; }
+
+// ============================================================================ host side
+struct TwTable {
+    cd* dev = nullptr;
+};
+
+std::mutex g_mu;
+std::map<int, TwTable> g_tables;
+
+// exp(-2 pi i t / TW_N) rounded from long double, with exact values on the axes.
+void host_twiddles(std::vector<cd>& h) {
+    h.resize(TW_N);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int t = 0; t < TW_N; ++t) {
+        // reduce to the first octant and rebuild by symmetry so that every entry is as
+        // accurate as the long-double evaluation of an angle in [0, pi/4]
+        const int q = t / (TW_N / 4), r = t % (TW_N / 4);
+        long double c, s;
+        if (r == 0) {
+            c = 1.0L;
+            s = 0.0L;
+        } else if (2 * r <= TW_N / 4) {
+            const long double a = 2.0L * pi * (long double)r / (long double)TW_N;
+            c = cosl(a);
+            s = sinl(a);
+        } else {
+            const long double a = 2.0L * pi * (long double)(TW_N / 4 - r) / (long double)TW_N;
+            c = sinl(a);
+            s = cosl(a);
+        }
+        // angle = q * pi/2 + theta with (cos theta, sin theta) = (c, s)
+        long double C, S;
+        switch (q) {
+            case 0: C = c; S = s; break;
+            case 1: C = -s; S = c; break;
+            case 2: C = -c; S = -s; break;
+            default: C = s; S = -c; break;
+        }
+        h[t] = cd{(double)C, (double)(-S)};  // exp(-i angle)
+    }
+}
+
+int get_table(const cd** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LOOP_EHIP;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tables.find(dev);
+    if (it != g_tables.end()) {
+        *out = it->second.dev;
+        return LOOP_OK;
+    }
+    std::vector<cd> h;
+    host_twiddles(h);
+    TwTable tb;
+    if (hipMalloc((void**)&tb.dev, sizeof(cd) * TW_N) != hipSuccess) return LOOP_EHIP;
+    if (hipMemcpy(tb.dev, h.data(), sizeof(cd) * TW_N, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(tb.dev);
+        return LOOP_EHIP;
+    }
+    g_tables[dev] = tb;
+    *out = tb.dev;
+    return LOOP_OK;
+}
+
+bool pow2_in_range(int n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0; }
+
+int check_shape(double L, int Nx, int Ns, int nloops) {
+    if (!(L > 0.0) || !std::isfinite(L)) return LOOP_EINVAL;
+    if (nloops < 1 || nloops > (1 << 20)) return LOOP_EINVAL;
+    if (Nx < 8 || Ns < 8 || Nx > 1024 || Ns > 1024) return LOOP_EINVAL;
+    if (!pow2_in_range(Nx) || !pow2_in_range(Ns)) return LOOP_ENOTSUP;
+    return LOOP_OK;
+}
+
+bool aligned(const void* p, size_t a) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+Shape make_shape(double L, int Nx, int Ns, int nloops) {
+    Shape s;
+    s.M = Nx;
+    s.N = Ns;
+    s.Kx = (Nx - 1) / 3;
+    s.Ks = (Ns - 1) / 3;
+    s.H = Nx / 2 + 1;
+    s.C = s.Kx + 1;
+    s.nloops = nloops;
+    s.L = L;
+    return s;
+}
+
+size_t round_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Work space layout: header | A | BD | Cb | Glin | partial | J | dJdT | Told
+size_t layout(const Shape& s, char* base, Work* w) {
+    size_t off = round_up(sizeof(WsHeader));
+    const size_t inter = (size_t)s.nloops * s.N * s.C * sizeof(cd);
+    const size_t glin = (size_t)s.nloops * (2 * s.Ks + 1) * s.C * sizeof(cd);
+    const size_t part = (size_t)s.nloops * s.C * 2 * sizeof(double);
+    const size_t scal = (size_t)s.nloops * sizeof(double);
+    Work ww{};
+    ww.status = reinterpret_cast<int*>(base);
+    ww.A = reinterpret_cast<cd*>(base + off); off = round_up(off + inter);
+    ww.BD = reinterpret_cast<cd*>(base + off); off = round_up(off + inter);
+    ww.Cb = reinterpret_cast<cd*>(base + off); off = round_up(off + inter);
+    ww.Glin = reinterpret_cast<cd*>(base + off); off = round_up(off + glin);
+    ww.partial = reinterpret_cast<double*>(base + off); off = round_up(off + part);
+    ww.J = reinterpret_cast<double*>(base + off); off = round_up(off + scal);
+    ww.dJdT = reinterpret_cast<double*>(base + off); off = round_up(off + scal);
+    ww.Told = reinterpret_cast<double*>(base + off); off = round_up(off + scal);
+    if (w) *w = ww;
+    return off;
+}
+
+int prepare(double L, int Nx, int Ns, int nloops, void* ws, size_t ws_bytes, Shape* sh, Work* w,
+            const cd** tw) {
+    int st = check_shape(L, Nx, Ns, nloops);
+    if (st) return st;
+    *sh = make_shape(L, Nx, Ns, nloops);
+    if (!aligned(ws, 256)) return LOOP_EINVAL;
+    if (layout(*sh, nullptr, nullptr) > ws_bytes) return LOOP_EWORKSPACE;
+    layout(*sh, static_cast<char*>(ws), w);
+    return get_table(tw);
+}
+
+// ---------------------------------------------------------------------------- launchers
+#define LO_SWITCH_SIZE(n, BODY)                     \
+    switch (n) {                                    \
+        case 8: { constexpr int S_ = 8; BODY; } break;       \
+        case 16: { constexpr int S_ = 16; BODY; } break;     \
+        case 32: { constexpr int S_ = 32; BODY; } break;     \
+        case 64: { constexpr int S_ = 64; BODY; } break;     \
+        case 128: { constexpr int S_ = 128; BODY; } break;   \
+        case 256: { constexpr int S_ = 256; BODY; } break;   \
+        case 512: { constexpr int S_ = 512; BODY; } break;   \
+        case 1024: { constexpr int S_ = 1024; BODY; } break; \
+        default: return LOOP_ENOTSUP;                        \
+    }
+
+unsigned col_blocks(const Shape& s) {
+    const int F = 2048 / s.N;
+    return (unsigned)(((size_t)s.nloops * s.C + F - 1) / F);
+}
+unsigned row_blocks(const Shape& s) {
+    const int rows = 4096 / s.M;
+    return (unsigned)(((size_t)s.nloops * s.N + rows - 1) / rows);
+}
+
+int launch_A(const Shape& s, const cd* uhat, const Work& w, const cd* tw, hipStream_t st) {
+    LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_colA<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, uhat, w, tw));
+    return LOOP_OK;
+}
+int launch_B(const Shape& s, const Work& w, const cd* tw, hipStream_t st) {
+    LO_SWITCH_SIZE(s.M, hipLaunchKernelGGL(k_rowB<S_>, dim3(row_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
+    return LOOP_OK;
+}
+int launch_C(const Shape& s, const cd* uhat, const double* T, const Work& w, cd* rhat, int mode, const cd* tw,
+             hipStream_t st) {
+    LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_colC<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, uhat, T, w,
+                                           rhat, mode, tw));
+    return LOOP_OK;
+}
+int launch_D(const Shape& s, const Work& w, double* T, int mode, double dtau, double* J_hist, double* Jout,
+             double* dJdTout, const cd* tw, hipStream_t st) {
+    LO_SWITCH_SIZE(s.M, hipLaunchKernelGGL(k_rowD<S_>, dim3(row_blocks(s)), dim3(kBlock), 0, st, s, w, T, mode,
+                                           dtau, J_hist, Jout, dJdTout, tw));
+    return LOOP_OK;
+}
+int launch_E(const Shape& s, cd* uhat, const Work& w, cd* Gout, int mode, double dtau, int scheme, const cd* tw,
+             hipStream_t st) {
+    LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_colE<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, uhat, w, Gout,
+                                           mode, dtau, scheme, tw));
+    return LOOP_OK;
+}
+
+unsigned elem_blocks(size_t n) {
+    size_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    return (unsigned)(b ? b : 1);
+}
+
+int last_error() { return hipGetLastError() == hipSuccess ? LOOP_OK : LOOP_EHIP; }
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+int loop_init(void) {
+    const cd* tw = nullptr;
+    return get_table(&tw);
+}
+
+int loop_shutdown(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int dev0 = 0;
+    hipGetDevice(&dev0);
+    for (auto& kv : g_tables) {
+        hipSetDevice(kv.first);
+        hipFree(kv.second.dev);
+    }
+    hipSetDevice(dev0);
+    g_tables.clear();
+    return LOOP_OK;
+}
+
+int loop_workspace_bytes(int Nx, int Ns, int nloops, size_t* bytes) {
+    if (!bytes) return LOOP_EINVAL;
+    int st = check_shape(1.0, Nx, Ns, nloops);
+    if (st) return st;
+    *bytes = layout(make_shape(1.0, Nx, Ns, nloops), nullptr, nullptr);
+    return LOOP_OK;
+}
+
+int loop_workspace_init(void* ws, size_t ws_bytes, void* stream) {
+    if (!aligned(ws, 256) || ws_bytes < sizeof(WsHeader)) return LOOP_EINVAL;
+    hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(1), 0, (hipStream_t)stream, (WsHeader*)ws);
+    return last_error();
+}
+
+int loop_residual(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat, double* rhat,
+                  void* ws, size_t ws_bytes, void* stream) {
+    Shape s;
+    Work w;
+    const cd* tw;
+    if (!aligned(T, 8) || !aligned(uhat, 16) || !aligned(rhat, 16) || (const void*)uhat == (const void*)rhat)
+        return LOOP_EINVAL;
+    int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
+    if (st) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    const cd* u = reinterpret_cast<const cd*>(uhat);
+    cd* r = reinterpret_cast<cd*>(rhat);
+    if ((st = launch_A(s, u, w, tw, hs))) return st;
+    if ((st = launch_B(s, w, tw, hs))) return st;
+    if ((st = launch_C(s, u, T, w, r, MODE_RESIDUAL, tw, hs))) return st;
+    if (s.H > s.C)
+        hipLaunchKernelGGL(k_zero_outer_cols, dim3(elem_blocks((size_t)s.nloops * s.N * (s.H - s.C))), dim3(256), 0,
+                           hs, s, r);
+    return last_error();
+}
+
+int loop_cost(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat, double* J, void* ws,
+              size_t ws_bytes, void* stream) {
+    Shape s;
+    Work w;
+    const cd* tw;
+    if (!aligned(T, 8) || !aligned(uhat, 16) || !aligned(J, 8)) return LOOP_EINVAL;
+    int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
+    if (st) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    const cd* u = reinterpret_cast<const cd*>(uhat);
+    if ((st = launch_A(s, u, w, tw, hs))) return st;
+    if ((st = launch_B(s, w, tw, hs))) return st;
+    if ((st = launch_C(s, u, T, w, nullptr, MODE_COST, tw, hs))) return st;
+    hipLaunchKernelGGL(k_finalize, dim3((nloops + 255) / 256), dim3(256), 0, hs, s, w, const_cast<double*>(T), J,
+                       (double*)nullptr);
+    return last_error();
+}
+
+int loop_adjoint_grad(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat, double* Ghat,
+                      double* dJdT, double* J, void* ws, size_t ws_bytes, void* stream) {
+    Shape s;
+    Work w;
+    const cd* tw;
+    if (!aligned(T, 8) || !aligned(uhat, 16) || !aligned(Ghat, 16) || (const void*)uhat == (const void*)Ghat)
+        return LOOP_EINVAL;
+    if ((dJdT && !aligned(dJdT, 8)) || (J && !aligned(J, 8))) return LOOP_EINVAL;
+    int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
+    if (st) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    const cd* u = reinterpret_cast<const cd*>(uhat);
+    cd* G = reinterpret_cast<cd*>(Ghat);
+    if ((st = launch_A(s, u, w, tw, hs))) return st;
+    if ((st = launch_B(s, w, tw, hs))) return st;
+    if ((st = launch_C(s, u, T, w, nullptr, MODE_GRAD, tw, hs))) return st;
+    if ((st = launch_D(s, w, const_cast<double*>(T), MODE_GRAD, 0.0, nullptr, J, dJdT, tw, hs))) return st;
+    if ((st = launch_E(s, nullptr, w, G, MODE_GRAD, 0.0, 0, tw, hs))) return st;
+    if (s.H > s.C)
+        hipLaunchKernelGGL(k_zero_outer_cols, dim3(elem_blocks((size_t)s.nloops * s.N * (s.H - s.C))), dim3(256), 0,
+                           hs, s, G);
+    return last_error();
+}
+
+int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau, int scheme, int nsteps,
+              double* J_hist, void* ws, size_t ws_bytes, void* stream) {
+    Shape s;
+    Work w;
+    const cd* tw;
+    if (!aligned(T, 8) || !aligned(uhat, 16) || (J_hist && !aligned(J_hist, 8))) return LOOP_EINVAL;
+    if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1) || nsteps < 0) return LOOP_EINVAL;
+    int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
+    if (st) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    cd* u = reinterpret_cast<cd*>(uhat);
+    hipLaunchKernelGGL(k_canonicalize, dim3(elem_blocks((size_t)s.nloops * s.N * s.H)), dim3(256), 0, hs, s, u);
+    for (int i = 0; i < nsteps; ++i) {
+        double* jh = J_hist ? J_hist + (size_t)i * nloops : nullptr;
+        if ((st = launch_A(s, u, w, tw, hs))) return st;
+        if ((st = launch_B(s, w, tw, hs))) return st;
+        if ((st = launch_C(s, u, T, w, nullptr, MODE_STEP, tw, hs))) return st;
+        if ((st = launch_D(s, w, T, MODE_STEP, dtau, jh, nullptr, nullptr, tw, hs))) return st;
+        if ((st = launch_E(s, u, w, nullptr, MODE_STEP, dtau, scheme, tw, hs))) return st;
+    }
+    return last_error();
+}
+
+int loop_update(double L, int Nx, int Ns, int nloops, double* T, double* uhat, const double* Ghat,
+                const double* dJdT, double dtau, int scheme, void* stream) {
+    int st = check_shape(L, Nx, Ns, nloops);
+    if (st) return st;
+    if (!aligned(T, 8) || !aligned(uhat, 16) || !aligned(Ghat, 16) || !aligned(dJdT, 8) ||
+        (const void*)uhat == (const void*)Ghat)
+        return LOOP_EINVAL;
+    if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1)) return LOOP_EINVAL;
+    Shape s = make_shape(L, Nx, Ns, nloops);
+    hipStream_t hs = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_update, dim3(elem_blocks((size_t)s.nloops * s.N * s.H)), dim3(256), 0, hs, s, T,
+                       reinterpret_cast<cd*>(uhat), reinterpret_cast<const cd*>(Ghat), dtau, scheme);
+    hipLaunchKernelGGL(k_update_T, dim3((nloops + 255) / 256), dim3(256), 0, hs, nloops, T, dJdT, dtau);
+    return last_error();
+}
+
+int loop_status_sync(void* ws, void* stream) {
+    if (!aligned(ws, 256)) return LOOP_EINVAL;
+    WsHeader h;
+    hipStream_t hs = (hipStream_t)stream;
+    if (hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, hs) != hipSuccess) return LOOP_EHIP;
+    if (hipStreamSynchronize(hs) != hipSuccess) return LOOP_EHIP;
+    if (h.magic != kWsMagic) return LOOP_EWORKSPACE;
+    if (h.status != 0) {
+        hipLaunchKernelGGL(k_ws_clear_status, dim3(1), dim3(1), 0, hs, (WsHeader*)ws);
+        if (last_error()) return LOOP_EHIP;
+    }
+    return h.status;
+}
+
+const char* loop_status_string(int status) {
+    switch (status) {
+        case LOOP_OK: return "ok";
+        case LOOP_EINVAL: return "invalid argument";
+        case LOOP_ENOTSUP: return "unsupported size";
+        case LOOP_EHIP: return "HIP runtime error";
+        case LOOP_ENONFINITE: return "non-finite or non-positive period or cost on device";
+        case LOOP_EWORKSPACE: return "work space too small or not initialised";
+        case LOOP_EHANG: return "batched scheduler dependency wait timed out";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"
