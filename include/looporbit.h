@@ -34,7 +34,7 @@
  *   work is queued. Nothing is queued when a check fails. Conditions that only the device
  *   can see (a non-finite or non-positive period, a non-finite cost) set a sticky status
  *   word in the work space, and loop_status_sync returns it.
- * - Sizes: Nx and Ns must be powers of two in [8, 1024]; 1 <= nloops <= 1<<20.
+ * - Sizes: Nx and Ns must be powers of two in [8, 1024]; 1 <= nloops <= 65535.
  */
 #ifndef LOOPORBIT_H
 #define LOOPORBIT_H

@@ -19,86 +19,96 @@ namespace {
 
 // ============================================================================ kernels
 template <int N>
-__global__ __launch_bounds__(kBlock) void k_colA(Shape sh, const cd* __restrict__ uhat, Work w,
-                                                 const cd* __restrict__ tw) {
-    __shared__ cd ex[2048];
-    col_pass_A<N>(sh, blockIdx.x, uhat, w, ex, tw);
+__global__ __launch_bounds__(kBlock) void k_colA(Shape sh, Work w, const cd* __restrict__ tw) {
+    __shared__ cd ex[ColG<N>::LDS];
+    col_pass_A<N>(sh, blockIdx.x, w, ex, tw);
 }
 
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_rowB(Shape sh, Work w, const cd* __restrict__ tw) {
-    __shared__ cd tile[RowGeom<M>::ROWS * RowGeom<M>::CMAX];
-    __shared__ cd ex[2048];
-    row_pass_B<M>(sh, blockIdx.x, w, tile, ex, tw);
+    __shared__ cd lds[RowG<M>::LDS];
+    row_pass_B<M>(sh, blockIdx.x, w, lds, tw);
 }
 
 template <int N>
-__global__ __launch_bounds__(kBlock) void k_colC(Shape sh, const cd* __restrict__ uhat,
-                                                 const double* __restrict__ T, Work w, cd* rhat_out, int mode,
-                                                 const cd* __restrict__ tw) {
-    __shared__ cd ex[2048];
-    col_pass_C<N>(sh, blockIdx.x, uhat, T, w, rhat_out, mode, ex, tw);
+__global__ __launch_bounds__(kBlock) void k_colC(Shape sh, const double* __restrict__ T, Work w, int mode,
+                                                 double dtau, int scheme, const cd* __restrict__ tw) {
+    __shared__ cd ex[ColG<N>::LDS];
+    __shared__ double red[2 * kBlock / 64];
+    col_pass_C<N>(sh, blockIdx.x, T, w, mode, dtau, scheme, ex, red, tw);
 }
 
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_rowD(Shape sh, Work w, double* T, int mode, double dtau,
                                                  double* J_hist, double* Jout, double* dJdTout,
                                                  const cd* __restrict__ tw) {
-    __shared__ cd tile[2 * RowGeom<M>::ROWS * RowGeom<M>::CMAX];
-    __shared__ cd ex[2048];
-    row_pass_D<M>(sh, blockIdx.x, w, T, mode, dtau, J_hist, Jout, dJdTout, tile, ex, tw);
+    __shared__ cd lds[RowG<M>::LDS];
+    row_pass_D<M>(sh, blockIdx.x, w, T, mode, dtau, J_hist, Jout, dJdTout, lds, tw);
 }
 
 template <int N>
-__global__ __launch_bounds__(kBlock) void k_colE(Shape sh, cd* uhat, Work w, cd* Gout, int mode, double dtau,
-                                                 int scheme, const cd* __restrict__ tw) {
-    __shared__ cd ex[2048];
-    col_pass_E<N>(sh, blockIdx.x, uhat, w, Gout, mode, dtau, scheme, ex, tw);
+__global__ __launch_bounds__(kBlock) void k_colE(Shape sh, Work w, int mode, double dtau, int scheme, int fuseA,
+                                                 const cd* __restrict__ tw) {
+    __shared__ cd ex[ColG<N>::LDS];
+    col_pass_E<N>(sh, blockIdx.x, w, mode, dtau, scheme, fuseA != 0, ex, tw);
 }
 
-__global__ void k_finalize(Shape sh, Work w, double* T, double* Jout, double* dJdTout) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l < sh.nloops) finalize_loop(sh, l, w, T, MODE_COST, 0.0, nullptr, Jout, dJdTout);
+// one wavefront per loop
+__global__ __launch_bounds__(64) void k_finalize(Shape sh, Work w, double* T, double* Jout, double* dJdTout) {
+    finalize_loop(sh, blockIdx.x, w, T, MODE_COST, 0.0, nullptr, Jout, dJdTout);
 }
 
-// Make a state canonical in place: band-limited, column 0 Hermitian.
-__global__ void k_canonicalize(Shape sh, cd* uhat) {
-    const size_t per = (size_t)sh.N * sh.H;
-    const size_t total = per * sh.nloops;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-        const size_t l = i / per;
-        const int e = (int)((i % per) / sh.H), j = (int)(i % sh.H);
-        cd* u = uhat + l * per;
-        const bool inb = band_row(e, sh.N, sh.Ks) >= 0 && j < sh.C;
-        if (j > 0) {
-            if (!inb) u[(size_t)e * sh.H + j] = cd{0.0, 0.0};
-        } else if (e <= sh.N / 2) {
-            const int e2 = (sh.N - e) & (sh.N - 1);
-            if (inb) {
-                const cd a = u[(size_t)e * sh.H], b = u[(size_t)e2 * sh.H];
-                const cd v{0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
-                u[(size_t)e * sh.H] = v;
-                u[(size_t)e2 * sh.H] = cconj(v);
-            } else {
-                u[(size_t)e * sh.H] = cd{0.0, 0.0};
-                u[(size_t)e2 * sh.H] = cd{0.0, 0.0};
+// rfft layout -> band layout U[l][j][kk], column 0 through its Hermitian part (32 x 32 tiles).
+__global__ __launch_bounds__(256) void k_to_band(Shape sh, const cd* __restrict__ uhat, cd* __restrict__ U) {
+    __shared__ cd tile[32][33];
+    const int l = blockIdx.z, kk0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    const int tx = threadIdx.x % 32, ty0 = threadIdx.x / 32;
+    const cd* u = uhat + (size_t)l * sh.N * sh.H;
+    for (int ty = ty0; ty < 32; ty += 8) {
+        const int kk = kk0 + ty, j = j0 + tx;
+        cd v{0.0, 0.0};
+        if (kk < sh.NB && j < sh.C) {
+            const int e = (kk <= sh.Ks) ? kk : kk + sh.N - sh.NB;
+            v = u[(size_t)e * sh.H + j];
+            if (j == 0) {
+                const cd pr = u[(size_t)((sh.N - e) & (sh.N - 1)) * sh.H];
+                v = cd{0.5 * (v.x + pr.x), 0.5 * (v.y - pr.y)};
             }
         }
+        tile[ty][tx] = v;
+    }
+    __syncthreads();
+    cd* dst = U + (size_t)l * sh.C * sh.NB;
+    for (int ty = ty0; ty < 32; ty += 8) {
+        const int j = j0 + ty, kk = kk0 + tx;
+        if (j < sh.C && kk < sh.NB) dst[(size_t)j * sh.NB + kk] = tile[tx][ty];
     }
 }
 
-// Zero columns j >= C of an rfft-layout output.
-__global__ void k_zero_outer_cols(Shape sh, cd* out) {
-    const int W = sh.H - sh.C;
-    const size_t total = (size_t)sh.nloops * sh.N * W;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-        const size_t row = i / W;
-        const int j = sh.C + (int)(i % W);
-        out[row * sh.H + j] = cd{0.0, 0.0};
+// band layout [l][j][kk] -> rfft layout, every entry written (0 outside the band).
+__global__ __launch_bounds__(256) void k_from_band(Shape sh, const cd* __restrict__ src, cd* __restrict__ out) {
+    __shared__ cd tile[32][33];
+    const int l = blockIdx.z, e0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    const int tx = threadIdx.x % 32, ty0 = threadIdx.x / 32;
+    const cd* s = src + (size_t)l * sh.C * sh.NB;
+    for (int ty = ty0; ty < 32; ty += 8) {
+        const int j = j0 + ty, e = e0 + tx;
+        cd v{0.0, 0.0};
+        if (j < sh.C && e < sh.N) {
+            const int kk = band_row(e, sh.N, sh.Ks);
+            if (kk >= 0) v = s[(size_t)j * sh.NB + kk];
+        }
+        tile[ty][tx] = v;
+    }
+    __syncthreads();
+    cd* o = out + (size_t)l * sh.N * sh.H;
+    for (int ty = ty0; ty < 32; ty += 8) {
+        const int e = e0 + ty, j = j0 + tx;
+        if (e < sh.N && j < sh.H) o[(size_t)e * sh.H + j] = tile[tx][ty];
     }
 }
 
-// uhat <- canonical(uhat) + dtau * sigma * Hermitian-part(Ghat) in the band, 0 outside.
+// uhat <- canonical(uhat) + dtau * sigma * Hermitian-part(Ghat) in the band, 0 outside (rfft layout).
 __global__ void k_update(Shape sh, const double* __restrict__ T, cd* uhat, const cd* __restrict__ Ghat,
                          double dtau, int scheme) {
     const size_t per = (size_t)sh.N * sh.H;
@@ -110,24 +120,29 @@ __global__ void k_update(Shape sh, const double* __restrict__ T, cd* uhat, const
         cd* u = uhat + l * per;
         const cd* g = Ghat + l * per;
         const bool inb = band_row(e, sh.N, sh.Ks) >= 0 && j < sh.C;
+        const int e2 = (sh.N - e) & (sh.N - 1);
         if (!inb) {
             u[(size_t)e * sh.H + j] = cd{0.0, 0.0};
-            if (j == 0) u[(size_t)((sh.N - e) & (sh.N - 1)) * sh.H] = cd{0.0, 0.0};
+            if (j == 0) u[(size_t)e2 * sh.H] = cd{0.0, 0.0};
             continue;
         }
-        const cd uu = load_state(u, e, j, sh.N, sh.H);
-        const cd gg = load_state(g, e, j, sh.N, sh.H);
+        cd uu = u[(size_t)e * sh.H + j], gg = g[(size_t)e * sh.H + j];
+        if (j == 0) {
+            const cd pu = u[(size_t)e2 * sh.H], pg = g[(size_t)e2 * sh.H];
+            uu = cd{0.5 * (uu.x + pu.x), 0.5 * (uu.y - pu.y)};
+            gg = cd{0.5 * (gg.x + pg.x), 0.5 * (gg.y - pg.y)};
+        }
         double sig = 1.0;
         if (scheme == 1) {
             const int k = (e < sh.N / 2) ? e : e - sh.N;
             const double q = kTwoPi * j / sh.L, q2 = q * q, q4 = q2 * q2;
             const double a = kTwoPi * k / T[l];
-            sig = 1.0 / (1.0 - dtau * (-a * a - q4 * q4 + 2.0 * q4 * q2 - q4));
+            sig = 1.0 / (1.0 - dtau * (-q4 * q4 + 2.0 * q4 * q2 - q4 - a * a));
         }
         const double s = dtau * sig;
         const cd v{uu.x + s * gg.x, uu.y + s * gg.y};
         u[(size_t)e * sh.H + j] = v;
-        if (j == 0) u[(size_t)((sh.N - e) & (sh.N - 1)) * sh.H] = cconj(v);
+        if (j == 0) u[(size_t)e2 * sh.H] = cconj(v);
     }
 }
 
@@ -218,7 +233,7 @@ bool pow2_in_range(int n) { return n >= 8 && n <= 1024 && (n & (n - 1)) == 0; }
 
 int check_shape(double L, int Nx, int Ns, int nloops) {
     if (!(L > 0.0) || !std::isfinite(L)) return LOOP_EINVAL;
-    if (nloops < 1 || nloops > (1 << 20)) return LOOP_EINVAL;
+    if (nloops < 1 || nloops > 65535) return LOOP_EINVAL;
     if (Nx < 8 || Ns < 8 || Nx > 1024 || Ns > 1024) return LOOP_EINVAL;
     if (!pow2_in_range(Nx) || !pow2_in_range(Ns)) return LOOP_ENOTSUP;
     return LOOP_OK;
@@ -234,6 +249,9 @@ Shape make_shape(double L, int Nx, int Ns, int nloops) {
     s.Ks = (Ns - 1) / 3;
     s.H = Nx / 2 + 1;
     s.C = s.Kx + 1;
+    s.NB = 2 * s.Ks + 1;
+    s.logN = 0;
+    while ((1 << s.logN) < Ns) ++s.logN;
     s.nloops = nloops;
     s.L = L;
     return s;
@@ -241,11 +259,11 @@ Shape make_shape(double L, int Nx, int Ns, int nloops) {
 
 size_t round_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Work space layout: header | A | BD | Cb | Glin | partial | J | dJdT | Told
+// Work space layout: header | A | BD | Cb | U | G | partial | J | dJdT | Told
 size_t layout(const Shape& s, char* base, Work* w) {
     size_t off = round_up(sizeof(WsHeader));
     const size_t inter = (size_t)s.nloops * s.N * s.C * sizeof(cd);
-    const size_t glin = (size_t)s.nloops * (2 * s.Ks + 1) * s.C * sizeof(cd);
+    const size_t band = (size_t)s.nloops * s.NB * s.C * sizeof(cd);
     const size_t part = (size_t)s.nloops * s.C * 2 * sizeof(double);
     const size_t scal = (size_t)s.nloops * sizeof(double);
     Work ww{};
@@ -253,7 +271,8 @@ size_t layout(const Shape& s, char* base, Work* w) {
     ww.A = reinterpret_cast<cd*>(base + off); off = round_up(off + inter);
     ww.BD = reinterpret_cast<cd*>(base + off); off = round_up(off + inter);
     ww.Cb = reinterpret_cast<cd*>(base + off); off = round_up(off + inter);
-    ww.Glin = reinterpret_cast<cd*>(base + off); off = round_up(off + glin);
+    ww.U = reinterpret_cast<cd*>(base + off); off = round_up(off + band);
+    ww.G = reinterpret_cast<cd*>(base + off); off = round_up(off + band);
     ww.partial = reinterpret_cast<double*>(base + off); off = round_up(off + part);
     ww.J = reinterpret_cast<double*>(base + off); off = round_up(off + scal);
     ww.dJdT = reinterpret_cast<double*>(base + off); off = round_up(off + scal);
@@ -288,26 +307,26 @@ int prepare(double L, int Nx, int Ns, int nloops, void* ws, size_t ws_bytes, Sha
     }
 
 unsigned col_blocks(const Shape& s) {
-    const int F = 2048 / s.N;
+    const int F = 8 * kBlock / s.N;  // columns per block
     return (unsigned)(((size_t)s.nloops * s.C + F - 1) / F);
 }
 unsigned row_blocks(const Shape& s) {
-    const int rows = 4096 / s.M;
+    const int rows = 2 * kBlock * (s.M >= 1024 ? 16 : 8) / s.M;
     return (unsigned)(((size_t)s.nloops * s.N + rows - 1) / rows);
 }
 
-int launch_A(const Shape& s, const cd* uhat, const Work& w, const cd* tw, hipStream_t st) {
-    LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_colA<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, uhat, w, tw));
+int launch_A(const Shape& s, const Work& w, const cd* tw, hipStream_t st) {
+    LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_colA<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
     return LOOP_OK;
 }
 int launch_B(const Shape& s, const Work& w, const cd* tw, hipStream_t st) {
     LO_SWITCH_SIZE(s.M, hipLaunchKernelGGL(k_rowB<S_>, dim3(row_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
     return LOOP_OK;
 }
-int launch_C(const Shape& s, const cd* uhat, const double* T, const Work& w, cd* rhat, int mode, const cd* tw,
+int launch_C(const Shape& s, const double* T, const Work& w, int mode, double dtau, int scheme, const cd* tw,
              hipStream_t st) {
-    LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_colC<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, uhat, T, w,
-                                           rhat, mode, tw));
+    LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_colC<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, T, w, mode,
+                                           dtau, scheme, tw));
     return LOOP_OK;
 }
 int launch_D(const Shape& s, const Work& w, double* T, int mode, double dtau, double* J_hist, double* Jout,
@@ -316,11 +335,19 @@ int launch_D(const Shape& s, const Work& w, double* T, int mode, double dtau, do
                                            dtau, J_hist, Jout, dJdTout, tw));
     return LOOP_OK;
 }
-int launch_E(const Shape& s, cd* uhat, const Work& w, cd* Gout, int mode, double dtau, int scheme, const cd* tw,
+int launch_E(const Shape& s, const Work& w, int mode, double dtau, int scheme, int fuseA, const cd* tw,
              hipStream_t st) {
-    LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_colE<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, uhat, w, Gout,
-                                           mode, dtau, scheme, tw));
+    LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_colE<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, mode, dtau,
+                                           scheme, fuseA, tw));
     return LOOP_OK;
+}
+void launch_to_band(const Shape& s, const cd* uhat, cd* U, hipStream_t st) {
+    dim3 grid((s.NB + 31) / 32, (s.C + 31) / 32, s.nloops);
+    hipLaunchKernelGGL(k_to_band, grid, dim3(256), 0, st, s, uhat, U);
+}
+void launch_from_band(const Shape& s, const cd* src, cd* out, hipStream_t st) {
+    dim3 grid((s.N + 31) / 32, (s.H + 31) / 32, s.nloops);
+    hipLaunchKernelGGL(k_from_band, grid, dim3(256), 0, st, s, src, out);
 }
 
 unsigned elem_blocks(size_t n) {
@@ -378,14 +405,11 @@ int loop_residual(double L, int Nx, int Ns, int nloops, const double* T, const d
     int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
     if (st) return st;
     hipStream_t hs = (hipStream_t)stream;
-    const cd* u = reinterpret_cast<const cd*>(uhat);
-    cd* r = reinterpret_cast<cd*>(rhat);
-    if ((st = launch_A(s, u, w, tw, hs))) return st;
+    launch_to_band(s, reinterpret_cast<const cd*>(uhat), w.U, hs);
+    if ((st = launch_A(s, w, tw, hs))) return st;
     if ((st = launch_B(s, w, tw, hs))) return st;
-    if ((st = launch_C(s, u, T, w, r, MODE_RESIDUAL, tw, hs))) return st;
-    if (s.H > s.C)
-        hipLaunchKernelGGL(k_zero_outer_cols, dim3(elem_blocks((size_t)s.nloops * s.N * (s.H - s.C))), dim3(256), 0,
-                           hs, s, r);
+    if ((st = launch_C(s, T, w, MODE_RESIDUAL, 0.0, 0, tw, hs))) return st;
+    launch_from_band(s, w.G, reinterpret_cast<cd*>(rhat), hs);
     return last_error();
 }
 
@@ -398,11 +422,11 @@ int loop_cost(double L, int Nx, int Ns, int nloops, const double* T, const doubl
     int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
     if (st) return st;
     hipStream_t hs = (hipStream_t)stream;
-    const cd* u = reinterpret_cast<const cd*>(uhat);
-    if ((st = launch_A(s, u, w, tw, hs))) return st;
+    launch_to_band(s, reinterpret_cast<const cd*>(uhat), w.U, hs);
+    if ((st = launch_A(s, w, tw, hs))) return st;
     if ((st = launch_B(s, w, tw, hs))) return st;
-    if ((st = launch_C(s, u, T, w, nullptr, MODE_COST, tw, hs))) return st;
-    hipLaunchKernelGGL(k_finalize, dim3((nloops + 255) / 256), dim3(256), 0, hs, s, w, const_cast<double*>(T), J,
+    if ((st = launch_C(s, T, w, MODE_COST, 0.0, 0, tw, hs))) return st;
+    hipLaunchKernelGGL(k_finalize, dim3(nloops), dim3(64), 0, hs, s, w, const_cast<double*>(T), J,
                        (double*)nullptr);
     return last_error();
 }
@@ -418,16 +442,13 @@ int loop_adjoint_grad(double L, int Nx, int Ns, int nloops, const double* T, con
     int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
     if (st) return st;
     hipStream_t hs = (hipStream_t)stream;
-    const cd* u = reinterpret_cast<const cd*>(uhat);
-    cd* G = reinterpret_cast<cd*>(Ghat);
-    if ((st = launch_A(s, u, w, tw, hs))) return st;
+    launch_to_band(s, reinterpret_cast<const cd*>(uhat), w.U, hs);
+    if ((st = launch_A(s, w, tw, hs))) return st;
     if ((st = launch_B(s, w, tw, hs))) return st;
-    if ((st = launch_C(s, u, T, w, nullptr, MODE_GRAD, tw, hs))) return st;
+    if ((st = launch_C(s, T, w, MODE_GRAD, 0.0, 0, tw, hs))) return st;
     if ((st = launch_D(s, w, const_cast<double*>(T), MODE_GRAD, 0.0, nullptr, J, dJdT, tw, hs))) return st;
-    if ((st = launch_E(s, nullptr, w, G, MODE_GRAD, 0.0, 0, tw, hs))) return st;
-    if (s.H > s.C)
-        hipLaunchKernelGGL(k_zero_outer_cols, dim3(elem_blocks((size_t)s.nloops * s.N * (s.H - s.C))), dim3(256), 0,
-                           hs, s, G);
+    if ((st = launch_E(s, w, MODE_GRAD, 0.0, 0, 0, tw, hs))) return st;
+    launch_from_band(s, w.G, reinterpret_cast<cd*>(Ghat), hs);
     return last_error();
 }
 
@@ -442,15 +463,16 @@ int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, dou
     if (st) return st;
     hipStream_t hs = (hipStream_t)stream;
     cd* u = reinterpret_cast<cd*>(uhat);
-    hipLaunchKernelGGL(k_canonicalize, dim3(elem_blocks((size_t)s.nloops * s.N * s.H)), dim3(256), 0, hs, s, u);
+    launch_to_band(s, u, w.U, hs);
+    if (nsteps > 0 && (st = launch_A(s, w, tw, hs))) return st;
     for (int i = 0; i < nsteps; ++i) {
         double* jh = J_hist ? J_hist + (size_t)i * nloops : nullptr;
-        if ((st = launch_A(s, u, w, tw, hs))) return st;
         if ((st = launch_B(s, w, tw, hs))) return st;
-        if ((st = launch_C(s, u, T, w, nullptr, MODE_STEP, tw, hs))) return st;
+        if ((st = launch_C(s, T, w, MODE_STEP, dtau, scheme, tw, hs))) return st;
         if ((st = launch_D(s, w, T, MODE_STEP, dtau, jh, nullptr, nullptr, tw, hs))) return st;
-        if ((st = launch_E(s, u, w, nullptr, MODE_STEP, dtau, scheme, tw, hs))) return st;
+        if ((st = launch_E(s, w, MODE_STEP, dtau, scheme, i + 1 < nsteps, tw, hs))) return st;
     }
+    launch_from_band(s, w.U, u, hs);
     return last_error();
 }
 
