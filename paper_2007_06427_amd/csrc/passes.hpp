@@ -307,35 +307,49 @@ struct RowG {
     static constexpr int NOUT = (2 * PW * CMAX + 63) / 64;  // split outputs per thread
 };
 
-// Load rows [g0, g0 + ROWS) of an intermediate into a tile[j][r] (stride TS), coalesced
-// along n. Rows past nrows read as zero. ROWS and N are powers of two.
-template <int ROWS>
-__device__ __forceinline__ void load_rows(cd* tile, int TS, const cd* __restrict__ X, size_t g0,
-                                          const Shape& sh, size_t nrows) {
+// Load rows [g0, g0 + ROWS) of NT intermediates X[0..NT) into tiles tile + i * TILE, laid
+// out [j][r] with stride TS, coalesced along n. Rows past nrows read as zero. Every global
+// load is issued before the first LDS store, so the loads of a tile are in flight together.
+// ROWS and N are powers of two.
+template <int ROWS, int CMAX, int TS, int TILE, int NT>
+__device__ __forceinline__ void load_rows(cd* tile, const cd* const (&X)[NT], size_t g0, const Shape& sh,
+                                          size_t nrows) {
+    constexpr int NL = (ROWS * CMAX + kBlock - 1) / kBlock;
     const int n = ROWS * sh.C;
-    for (int i = threadIdx.x; i < n; i += kBlock) {
+    cd buf[NT][NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = threadIdx.x + k * kBlock;
         const int j = i / ROWS, r = i % ROWS;
         const size_t g = g0 + r;
-        cd v{0.0, 0.0};
-        if (g < nrows) {
-            const size_t l = g >> sh.logN, nn = g & (size_t)(sh.N - 1);
-            v = X[(l * sh.C + j) * sh.N + nn];
+        const bool ok = i < n && g < nrows;
+        const size_t off = ok ? ((g >> sh.logN) * sh.C + j) * sh.N + (g & (size_t)(sh.N - 1)) : 0;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) buf[q][k] = ok ? X[q][off] : cd{0.0, 0.0};
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = threadIdx.x + k * kBlock;
+        if (i < n) {
+            const int j = i / ROWS, r = i % ROWS;
+#pragma unroll
+            for (int q = 0; q < NT; ++q) tile[q * TILE + j * TS + r] = buf[q][k];
         }
-        tile[j * TS + r] = v;
     }
 }
 
-template <int ROWS>
+template <int ROWS, int CMAX>
 __device__ __forceinline__ void store_rows(const cd* tile, int TS, cd* X, size_t g0, const Shape& sh,
                                            size_t nrows) {
+    constexpr int NL = (ROWS * CMAX + kBlock - 1) / kBlock;
     const int n = ROWS * sh.C;
-    for (int i = threadIdx.x; i < n; i += kBlock) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int i = threadIdx.x + k * kBlock;
         const int j = i / ROWS, r = i % ROWS;
         const size_t g = g0 + r;
-        if (g < nrows) {
-            const size_t l = g >> sh.logN, nn = g & (size_t)(sh.N - 1);
-            X[(l * sh.C + j) * sh.N + nn] = tile[j * TS + r];
-        }
+        if (i < n && g < nrows)
+            X[((g >> sh.logN) * sh.C + j) * sh.N + (g & (size_t)(sh.N - 1))] = tile[j * TS + r];
     }
 }
 
@@ -408,7 +422,10 @@ __device__ __forceinline__ void row_pass_B(const Shape& sh, int block, const Wor
     const int t = threadIdx.x % G::TPF, p = threadIdx.x / G::TPF;
     TwCache<M, G::PT> twc;
     tw_cache_load<M, G::PT>(twc, t, tw);
-    load_rows<G::ROWS>(lds, G::TS, w.A, g0, sh, nrows);
+    {
+        const cd* const src[1] = {w.A};
+        load_rows<G::ROWS, G::CMAX, G::TS, G::TILE, 1>(lds, src, g0, sh, nrows);
+    }
     __syncthreads();
     const double dq = kTwoPi / sh.L;
     cd va[G::PT], vb[G::PT];
@@ -422,7 +439,7 @@ __device__ __forceinline__ void row_pass_B(const Shape& sh, int block, const Wor
         vb[m] = pack2(a, cd{-q * a.y, q * a.x});  // row b
     }
     row_products<M>(sh, va, vb, lds, t, p, twc);
-    store_rows<G::ROWS>(lds, G::TS, w.BD, g0, sh, nrows);
+    store_rows<G::ROWS, G::CMAX>(lds, G::TS, w.BD, g0, sh, nrows);
 }
 
 // Sum the per-column partials of loop l into J, dJ/dT; in MODE_STEP also advance T.
@@ -476,8 +493,10 @@ __device__ __forceinline__ void row_pass_D(const Shape& sh, int block, const Wor
     const int t = threadIdx.x % G::TPF, p = threadIdx.x / G::TPF;
     TwCache<M, G::PT> twc;
     tw_cache_load<M, G::PT>(twc, t, tw);
-    load_rows<G::ROWS>(tA, G::TS, w.A, g0, sh, nrows);
-    load_rows<G::ROWS>(tC, G::TS, w.Cb, g0, sh, nrows);
+    {
+        const cd* const src[2] = {w.A, w.Cb};
+        load_rows<G::ROWS, G::CMAX, G::TS, G::TILE, 2>(tA, src, g0, sh, nrows);
+    }
     __syncthreads();
     cd va[G::PT], vb[G::PT];
 #pragma unroll
@@ -487,7 +506,7 @@ __device__ __forceinline__ void row_pass_D(const Shape& sh, int block, const Wor
         vb[m] = pack2(herm_ext(tA, G::TS, G::P + p, e, M, sh.Kx), herm_ext(tC, G::TS, G::P + p, e, M, sh.Kx));
     }
     row_products<M>(sh, va, vb, lds, t, p, twc);
-    store_rows<G::ROWS>(lds, G::TS, w.BD, g0, sh, nrows);
+    store_rows<G::ROWS, G::CMAX>(lds, G::TS, w.BD, g0, sh, nrows);
 }
 
 }  // namespace lo
