@@ -102,6 +102,27 @@ int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, dou
 int loop_update(double L, int Nx, int Ns, int nloops, double* T, double* uhat,
                 const double* Ghat, const double* dJdT, double dtau, int scheme, void* stream);
 
+/* ---- Batched form: loops of uneven (L, Nx, Ns) advanced together by one persistent kernel.
+ * The step is the one loop_step takes (Sec. 4.2), applied to every loop of the batch.
+ *
+ * loop_batch_create builds a plan on the current device. This host call allocates the
+ * plan's device tables, so it must run outside stream capture. Each loop needs a power-of-
+ * two Nx in [8, 512] and Ns in [8, 1024]. The loops' spectra live back to back in one
+ * rfft-layout pool, in the order given, at the offsets loop_batch_info reports (in complex
+ * values). Periods T[nloops]; J_hist, if not NULL, is [nsteps][nloops].
+ *
+ * loop_batch_step queues three kernels on `stream`, and allocates and synchronises nothing:
+ * a conversion into band layout (which also makes every loop canonical), the persistent
+ * step kernel (all nsteps steps in one launch), and the conversion back. Its work space
+ * (loop_batch_info bytes) must be prepared once by loop_batch_workspace_init. After a
+ * LOOP_EHANG status, prepare it again before reuse. */
+int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns, void** plan);
+int loop_batch_destroy(void* plan);
+int loop_batch_info(const void* plan, size_t* ws_bytes, size_t* pool_elems, long long* uhat_offsets);
+int loop_batch_workspace_init(const void* plan, void* ws, size_t ws_bytes, void* stream);
+int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau, int scheme,
+                    int nsteps, double* J_hist, void* ws, size_t ws_bytes, void* stream);
+
 /* Read (and clear) the sticky device status of a work space. Waits for `stream`. */
 int loop_status_sync(void* ws, void* stream);
 

@@ -147,3 +147,76 @@ def loop_update(uhat: torch.Tensor, T: torch.Tensor, L: float, Ghat: torch.Tenso
     check(_lib.lib().loop_update(float(L), Nx, Ns, nl, _ptr(T), _ptr(uhat), _ptr(Ghat), _ptr(dJdT), float(dtau),
                                  int(scheme), _stream_ptr()), "loop_update")
     return uhat, T
+
+
+class Batch:
+    """Loops of uneven (L, Nx, Ns) advanced together by the persistent batched kernel.
+
+    The spectra live back to back in one complex128 pool (rfft layout per loop, in the order
+    given); `offsets[l]` is loop l's first element. The plan's device tables and the work
+    space are allocated here, once, so that `step` can be captured into a graph.
+    """
+
+    def __init__(self, shapes, device=None):
+        self.shapes = [(float(L), int(Nx), int(Ns)) for (L, Nx, Ns) in shapes]
+        n = len(self.shapes)
+        Ls = (ctypes.c_double * n)(*[s[0] for s in self.shapes])
+        Nxs = (ctypes.c_int * n)(*[s[1] for s in self.shapes])
+        Nss = (ctypes.c_int * n)(*[s[2] for s in self.shapes])
+        plan = ctypes.c_void_p()
+        check(_lib.lib().loop_batch_create(n, Ls, Nxs, Nss, ctypes.byref(plan)), "loop_batch_create")
+        self._plan = plan
+        wsb, pe = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        offs = (ctypes.c_longlong * n)()
+        check(_lib.lib().loop_batch_info(plan, ctypes.byref(wsb), ctypes.byref(pe), offs), "loop_batch_info")
+        self.pool_elems = int(pe.value)
+        self.offsets = [int(o) for o in offs]
+        self.nloops = n
+        device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.ws = torch.empty(max(int(wsb.value), 256), dtype=torch.uint8, device=device)
+        check(_lib.lib().loop_batch_workspace_init(plan, _ptr(self.ws), self.ws.numel(), _stream_ptr()),
+              "loop_batch_workspace_init")
+
+    def pack(self, spectra):
+        """Pool tensor holding the given per-loop spectra (each (Ns, Nx//2+1) complex128)."""
+        dev = self.ws.device
+        pool = torch.zeros(self.pool_elems, dtype=torch.complex128, device=dev)
+        for (L, Nx, Ns), off, u in zip(self.shapes, self.offsets, spectra):
+            u = torch.as_tensor(u).to(dev).reshape(-1)
+            if u.numel() != Ns * (Nx // 2 + 1):
+                raise ValueError("spectrum shape does not match the plan")
+            pool[off:off + u.numel()] = u
+        return pool
+
+    def unpack(self, pool):
+        """Views of the pool, one (Ns, Nx//2+1) tensor per loop."""
+        return [pool[off:off + Ns * (Nx // 2 + 1)].view(Ns, Nx // 2 + 1)
+                for (L, Nx, Ns), off in zip(self.shapes, self.offsets)]
+
+    def step(self, pool, T, dtau, scheme=EXPLICIT, nsteps=1, J_hist=None):
+        if pool.dtype != torch.complex128 or pool.numel() != self.pool_elems or not pool.is_contiguous():
+            raise ValueError("pool must be the contiguous complex128 pool of this plan")
+        if T.dtype != torch.float64 or T.numel() != self.nloops or not T.is_contiguous():
+            raise ValueError("T must be float64 with one entry per loop")
+        if J_hist is not None and (J_hist.dtype != torch.float64 or J_hist.numel() < nsteps * self.nloops):
+            raise ValueError("J_hist must be float64 (nsteps, nloops)")
+        jh = _ptr(J_hist) if J_hist is not None else None
+        check(_lib.lib().loop_batch_step(self._plan, _ptr(T), _ptr(pool), float(dtau), int(scheme), int(nsteps), jh,
+                                         _ptr(self.ws), self.ws.numel(), _stream_ptr()), "loop_batch_step")
+        return pool, T
+
+    def status(self) -> int:
+        return int(_lib.lib().loop_status_sync(_ptr(self.ws), _stream_ptr()))
+
+    def reset(self):
+        """Prepare the work space again (needed after a LOOP_EHANG status)."""
+        check(_lib.lib().loop_batch_workspace_init(self._plan, _ptr(self.ws), self.ws.numel(), _stream_ptr()),
+              "loop_batch_workspace_init")
+
+    def __del__(self):
+        try:
+            if getattr(self, "_plan", None) is not None and self._plan.value:
+                _lib.lib().loop_batch_destroy(self._plan)
+                self._plan = None
+        except Exception:
+            pass

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -165,6 +166,265 @@ __global__ void k_ws_init(WsHeader* h) {
 }
 
 __global__ void k_ws_clear_status(WsHeader* h) { h->status = 0; }
+
+// ============================================================================ batched scheduler
+// A batch of loops of uneven shape advances in one persistent launch. The launch works
+// through a fixed, totally ordered list of items (pass, loop, tile):
+//   the A tiles of every loop, then for each step the B, C, D and E tiles of every loop.
+// Blocks take items in list order from a global counter. Before an item of loop l runs, its
+// block waits until loop l's completion counter shows that every earlier item of loop l is
+// done. Pass p of a step needs all of pass p-1, and pass B of the next step needs all of the
+// previous pass E (which also wrote the next pass A). An item depends only on items earlier in
+// the list, and a block that has taken an item is running. So the earliest unfinished item
+// can always proceed, and the launch cannot deadlock. Every wait is still bounded in time:
+// if one runs out, the block raises an abort flag that every other wait also checks, the
+// status becomes LOOP_EHANG, and all blocks leave.
+//
+// Completion counters live in the work space. The block that finishes a loop's last item
+// resets that loop's counter, and the last block to leave resets the item counter. A
+// work space is therefore ready for the next launch on the same stream.
+struct WsOff {  // byte offsets of one loop's regions inside the work space
+    size_t A, BD, Cb, U, G, partial, J, dJdT, Told;
+};
+
+struct BatchLoop {
+    Shape sh;    // this loop alone (nloops = 1)
+    WsOff off;
+    size_t uoff;  // offset of the loop's spectrum in the rfft-layout pool (complex values)
+    int nt[5];    // tiles of passes A, B, C, D, E
+    int ipl;      // items per step: B + C + D + E tiles
+};
+
+struct BatchQueue {
+    int next;    // next item to hand out
+    int exited;  // blocks that have left
+    int abort;   // raised when a bounded wait runs out
+    int pad;
+};
+
+enum : int { PASS_A = 0, PASS_B = 1, PASS_C = 2, PASS_D = 3, PASS_E = 4 };
+
+__host__ __device__ inline uint32_t item_code(int l, int pass, int tile) {
+    return ((uint32_t)l << 16) | ((uint32_t)pass << 13) | (uint32_t)tile;
+}
+
+struct BatchArgs {
+    const BatchLoop* loops;
+    const uint32_t* items;  // nA prologue items, then the ips items of one step
+    int nloops, nA, ips, nsteps;
+    BatchQueue* q;
+    int* done;  // [nloops] completion counters
+    char* ws;
+    int* status;
+    double* T;
+    double* J_hist;  // [nsteps][nloops] or null
+    double dtau;
+    int scheme;
+    const cd* tw;
+};
+
+constexpr uint64_t kSpinTicks = 200000000ull;  // 2 s of the 100 MHz constant clock
+
+__device__ __forceinline__ Work batch_work(const BatchLoop& b, char* ws, int* status) {
+    Work w;
+    w.A = reinterpret_cast<cd*>(ws + b.off.A);
+    w.BD = reinterpret_cast<cd*>(ws + b.off.BD);
+    w.Cb = reinterpret_cast<cd*>(ws + b.off.Cb);
+    w.U = reinterpret_cast<cd*>(ws + b.off.U);
+    w.G = reinterpret_cast<cd*>(ws + b.off.G);
+    w.partial = reinterpret_cast<double*>(ws + b.off.partial);
+    w.J = reinterpret_cast<double*>(ws + b.off.J);
+    w.dJdT = reinterpret_cast<double*>(ws + b.off.dJdT);
+    w.Told = reinterpret_cast<double*>(ws + b.off.Told);
+    w.status = status;
+    return w;
+}
+
+// Wait until *cnt >= target. Returns 1 when the launch is being abandoned.
+__device__ int wait_count(int* cnt, int target, BatchQueue* q, int* status) {
+    if (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) return 0;
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        __builtin_amdgcn_s_sleep(2);
+        if (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) return 0;
+        if (__hip_atomic_load(&q->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 1;
+        if (wall_clock64() - t0 > kSpinTicks) {
+            atomicExch(&q->abort, 1);
+            atomicCAS(status, 0, LOOP_EHANG);
+            return 1;
+        }
+    }
+}
+
+#define LO_CASE_ROW(M_, CALL) case M_: { constexpr int S_ = M_; CALL; } break;
+#define LO_ROW_SWITCH(m, CALL)                                                                       \
+    switch (m) {                                                                                     \
+        LO_CASE_ROW(8, CALL) LO_CASE_ROW(16, CALL) LO_CASE_ROW(32, CALL) LO_CASE_ROW(64, CALL)      \
+        LO_CASE_ROW(128, CALL) LO_CASE_ROW(256, CALL) LO_CASE_ROW(512, CALL) default: break;         \
+    }
+#define LO_COL_SWITCH(n, CALL)                                                                       \
+    switch (n) {                                                                                     \
+        LO_CASE_ROW(8, CALL) LO_CASE_ROW(16, CALL) LO_CASE_ROW(32, CALL) LO_CASE_ROW(64, CALL)      \
+        LO_CASE_ROW(128, CALL) LO_CASE_ROW(256, CALL) LO_CASE_ROW(512, CALL)                         \
+        LO_CASE_ROW(1024, CALL) default: break;                                                      \
+    }
+
+// One pass body per (pass, size), each compiled as its own function so that register
+// allocation is per body rather than over the union of all bodies.
+template <int N>
+__device__ __noinline__ void bk_A(const Shape& sh, int tile, const Work& w, cd* lds, const cd* tw) {
+    col_pass_A<N>(sh, tile, w, lds, tw);
+}
+template <int M>
+__device__ __noinline__ void bk_B(const Shape& sh, int tile, const Work& w, cd* lds, const cd* tw) {
+    row_pass_B<M>(sh, tile, w, lds, tw);
+}
+template <int N>
+__device__ __noinline__ void bk_C(const Shape& sh, int tile, const double* T, const Work& w, double dtau,
+                                  int scheme, cd* lds, double* red, const cd* tw) {
+    col_pass_C<N>(sh, tile, T, w, MODE_STEP, dtau, scheme, lds, red, tw);
+}
+template <int M>
+__device__ __noinline__ void bk_D(const Shape& sh, int tile, const Work& w, double* T, double dtau, double* jh,
+                                  cd* lds, const cd* tw) {
+    row_pass_D<M>(sh, tile, w, T, MODE_STEP, dtau, jh, nullptr, nullptr, lds, tw);
+}
+template <int N>
+__device__ __noinline__ void bk_E(const Shape& sh, int tile, const Work& w, double dtau, int scheme, int fuseA,
+                                  cd* lds, const cd* tw) {
+    col_pass_E<N>(sh, tile, w, MODE_STEP, dtau, scheme, fuseA != 0, lds, tw);
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
+    extern __shared__ cd lds[];
+    __shared__ double red[2 * kBlock / 64];
+    __shared__ int s_item, s_stop;
+    const int total = a.nA + a.nsteps * a.ips;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&a.q->next, 1);
+        __syncthreads();
+        const int i = s_item;
+        if (i >= total) break;
+        int s = 0;
+        uint32_t code;
+        if (i < a.nA) {
+            code = a.items[i];
+        } else {
+            s = (i - a.nA) / a.ips;
+            code = a.items[a.nA + (i - a.nA) % a.ips];
+        }
+        const int l = (int)(code >> 16), pass = (int)((code >> 13) & 7), tile = (int)(code & 0x1fff);
+        const BatchLoop b = a.loops[l];
+        int target = 0;
+        if (pass != PASS_A) {
+            target = b.nt[PASS_A] + s * b.ipl;
+            for (int p = PASS_B; p < pass; ++p) target += b.nt[p];
+        }
+        if (threadIdx.x == 0) s_stop = wait_count(&a.done[l], target, a.q, a.status);
+        __syncthreads();
+        if (s_stop) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const Work w = batch_work(b, a.ws, a.status);
+        const Shape& sh = b.sh;
+        switch (pass) {
+            case PASS_A:
+                LO_COL_SWITCH(sh.N, bk_A<S_>(sh, tile, w, lds, a.tw));
+                break;
+            case PASS_B:
+                LO_ROW_SWITCH(sh.M, bk_B<S_>(sh, tile, w, lds, a.tw));
+                break;
+            case PASS_C:
+                LO_COL_SWITCH(sh.N, bk_C<S_>(sh, tile, a.T + l, w, a.dtau, a.scheme, lds, red, a.tw));
+                break;
+            case PASS_D: {
+                double* jh = a.J_hist ? a.J_hist + (size_t)s * a.nloops + l : nullptr;
+                LO_ROW_SWITCH(sh.M, bk_D<S_>(sh, tile, w, a.T + l, a.dtau, jh, lds, a.tw));
+                break;
+            }
+            default:
+                LO_COL_SWITCH(sh.N, bk_E<S_>(sh, tile, w, a.dtau, a.scheme, s + 1 < a.nsteps, lds, a.tw));
+                break;
+        }
+        __threadfence();  // release this thread's results at agent scope
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();  // covers the block's writes ordered before it by the barrier
+            const int need = b.nt[PASS_A] + a.nsteps * b.ipl;
+            if (atomicAdd(&a.done[l], 1) + 1 == need) atomicExch(&a.done[l], 0);
+        }
+    }
+    if (threadIdx.x == 0 && atomicAdd(&a.q->exited, 1) == (int)gridDim.x - 1) {
+        atomicExch(&a.q->next, 0);
+        atomicExch(&a.q->exited, 0);
+    }
+}
+
+// rfft-layout pool -> per-loop band state (blockIdx.z = loop); see k_to_band.
+__global__ __launch_bounds__(256) void k_to_band_batch(const BatchLoop* loops, const cd* __restrict__ pool,
+                                                       char* ws) {
+    __shared__ cd tile[32][33];
+    const BatchLoop& b = loops[blockIdx.z];
+    const Shape& sh = b.sh;
+    const int kk0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    if (kk0 >= sh.NB || j0 >= sh.C) return;
+    const int tx = threadIdx.x % 32, ty0 = threadIdx.x / 32;
+    const cd* u = pool + b.uoff;
+    for (int ty = ty0; ty < 32; ty += 8) {
+        const int kk = kk0 + ty, j = j0 + tx;
+        cd v{0.0, 0.0};
+        if (kk < sh.NB && j < sh.C) {
+            const int e = (kk <= sh.Ks) ? kk : kk + sh.N - sh.NB;
+            v = u[(size_t)e * sh.H + j];
+            if (j == 0) {
+                const cd pr = u[(size_t)((sh.N - e) & (sh.N - 1)) * sh.H];
+                v = cd{0.5 * (v.x + pr.x), 0.5 * (v.y - pr.y)};
+            }
+        }
+        tile[ty][tx] = v;
+    }
+    __syncthreads();
+    cd* dst = reinterpret_cast<cd*>(ws + b.off.U);
+    for (int ty = ty0; ty < 32; ty += 8) {
+        const int j = j0 + ty, kk = kk0 + tx;
+        if (j < sh.C && kk < sh.NB) dst[(size_t)j * sh.NB + kk] = tile[tx][ty];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_from_band_batch(const BatchLoop* loops, const char* ws,
+                                                         cd* __restrict__ pool) {
+    __shared__ cd tile[32][33];
+    const BatchLoop& b = loops[blockIdx.z];
+    const Shape& sh = b.sh;
+    const int e0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    if (e0 >= sh.N || j0 >= sh.H) return;
+    const int tx = threadIdx.x % 32, ty0 = threadIdx.x / 32;
+    const cd* src = reinterpret_cast<const cd*>(ws + b.off.U);
+    for (int ty = ty0; ty < 32; ty += 8) {
+        const int j = j0 + ty, e = e0 + tx;
+        cd v{0.0, 0.0};
+        if (j < sh.C && e < sh.N) {
+            const int kk = band_row(e, sh.N, sh.Ks);
+            if (kk >= 0) v = src[(size_t)j * sh.NB + kk];
+        }
+        tile[ty][tx] = v;
+    }
+    __syncthreads();
+    cd* o = pool + b.uoff;
+    for (int ty = ty0; ty < 32; ty += 8) {
+        const int e = e0 + ty, j = j0 + tx;
+        if (e < sh.N && j < sh.H) o[(size_t)e * sh.H + j] = tile[tx][ty];
+    }
+}
+
+__global__ void k_batch_ws_init(BatchQueue* q, int* done, int nloops) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        q->next = 0;
+        q->exited = 0;
+        q->abort = 0;
+    }
+    if (i < nloops) done[i] = 0;
+}
 
 // ============================================================================ host side
 struct TwTable {
@@ -350,6 +610,43 @@ void launch_from_band(const Shape& s, const cd* src, cd* out, hipStream_t st) {
     hipLaunchKernelGGL(k_from_band, grid, dim3(256), 0, st, s, src, out);
 }
 
+// ---------------------------------------------------------------------------- batch plans
+struct BatchPlan {
+    int device = -1;
+    int nloops = 0;
+    std::vector<BatchLoop> loops;
+    BatchLoop* d_loops = nullptr;
+    uint32_t* d_items = nullptr;
+    int nA = 0, ips = 0;
+    size_t ws_bytes = 0, q_off = 0, done_off = 0, pool_elems = 0;
+    int max_nb = 1, max_c = 1, max_n = 1, max_h = 1;
+    size_t lds_bytes = 0;
+    int grid = 1;
+};
+
+int col_tiles(const Shape& s) { return (s.C + 2048 / s.N - 1) / (2048 / s.N); }
+int row_tiles(const Shape& s) {
+    const int rows = 4096 / s.M;
+    return (s.N + rows - 1) / rows;
+}
+size_t pass_lds_bytes(const Shape& s) {
+    const size_t col = 2304;  // F * (N + N/8) with F = 2048 / N
+    const int rows = 4096 / s.M, cmax = (s.M - 1) / 3 + 1;
+    const size_t row = std::max<size_t>(2 * (size_t)cmax * (rows + 1), 2304);
+    return std::max(col, row) * sizeof(cd);
+}
+
+void free_plan(BatchPlan* p) {
+    if (!p) return;
+    int dev0 = 0;
+    hipGetDevice(&dev0);
+    if (p->device >= 0) hipSetDevice(p->device);
+    if (p->d_loops) hipFree(p->d_loops);
+    if (p->d_items) hipFree(p->d_items);
+    hipSetDevice(dev0);
+    delete p;
+}
+
 unsigned elem_blocks(size_t n) {
     size_t b = (n + 255) / 256;
     if (b > 65536) b = 65536;
@@ -489,6 +786,159 @@ int loop_update(double L, int Nx, int Ns, int nloops, double* T, double* uhat, c
     hipLaunchKernelGGL(k_update, dim3(elem_blocks((size_t)s.nloops * s.N * s.H)), dim3(256), 0, hs, s, T,
                        reinterpret_cast<cd*>(uhat), reinterpret_cast<const cd*>(Ghat), dtau, scheme);
     hipLaunchKernelGGL(k_update_T, dim3((nloops + 255) / 256), dim3(256), 0, hs, nloops, T, dJdT, dtau);
+    return last_error();
+}
+
+int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns, void** plan) {
+    if (!plan || !L || !Nx || !Ns || nloops < 1 || nloops > 65535) return LOOP_EINVAL;
+    *plan = nullptr;
+    for (int l = 0; l < nloops; ++l) {
+        const int st = check_shape(L[l], Nx[l], Ns[l], 1);
+        if (st) return st;
+        if (Nx[l] > 512) return LOOP_ENOTSUP;  // batched row passes take Nx <= 512
+    }
+    const cd* tw;
+    int st = get_table(&tw);
+    if (st) return st;
+    BatchPlan* p = new BatchPlan();
+    hipGetDevice(&p->device);
+    p->nloops = nloops;
+    p->loops.resize(nloops);
+    // work space: header | queue | done[nloops] | per-loop regions
+    size_t off = round_up(sizeof(WsHeader));
+    p->q_off = off;
+    off = round_up(off + sizeof(BatchQueue));
+    p->done_off = off;
+    off = round_up(off + sizeof(int) * (size_t)nloops);
+    size_t pool = 0;
+    for (int l = 0; l < nloops; ++l) {
+        BatchLoop& b = p->loops[l];
+        b.sh = make_shape(L[l], Nx[l], Ns[l], 1);
+        Work w;
+        const size_t sz = layout(b.sh, reinterpret_cast<char*>(off), &w);
+        const size_t base = off;
+        auto rel = [&](const void* q) { return (size_t)reinterpret_cast<uintptr_t>(q); };
+        b.off = WsOff{rel(w.A), rel(w.BD), rel(w.Cb), rel(w.U), rel(w.G), rel(w.partial), rel(w.J), rel(w.dJdT),
+                      rel(w.Told)};
+        off = round_up(base + sz);
+        b.uoff = pool;
+        pool += (size_t)b.sh.N * b.sh.H;
+        b.nt[PASS_A] = col_tiles(b.sh);
+        b.nt[PASS_B] = row_tiles(b.sh);
+        b.nt[PASS_C] = col_tiles(b.sh);
+        b.nt[PASS_D] = row_tiles(b.sh);
+        b.nt[PASS_E] = col_tiles(b.sh);
+        b.ipl = b.nt[PASS_B] + b.nt[PASS_C] + b.nt[PASS_D] + b.nt[PASS_E];
+        p->max_nb = std::max(p->max_nb, b.sh.NB);
+        p->max_c = std::max(p->max_c, b.sh.C);
+        p->max_n = std::max(p->max_n, b.sh.N);
+        p->max_h = std::max(p->max_h, b.sh.H);
+        p->lds_bytes = std::max(p->lds_bytes, pass_lds_bytes(b.sh));
+    }
+    p->ws_bytes = off;
+    p->pool_elems = pool;
+    // item list: larger loops first within each pass, so that they start early
+    std::vector<int> order(nloops);
+    for (int l = 0; l < nloops; ++l) order[l] = l;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (size_t)p->loops[a].sh.M * p->loops[a].sh.N > (size_t)p->loops[b].sh.M * p->loops[b].sh.N;
+    });
+    std::vector<uint32_t> items;
+    for (int l : order)
+        for (int t = 0; t < p->loops[l].nt[PASS_A]; ++t) items.push_back(item_code(l, PASS_A, t));
+    p->nA = (int)items.size();
+    for (int pass = PASS_B; pass <= PASS_E; ++pass)
+        for (int l : order)
+            for (int t = 0; t < p->loops[l].nt[pass]; ++t) items.push_back(item_code(l, pass, t));
+    p->ips = (int)items.size() - p->nA;
+    // one resident wave of blocks
+    int per_cu = 1, cus = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBlock, p->lds_bytes) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) {
+        free_plan(p);
+        return LOOP_EHIP;
+    }
+    p->grid = std::max(1, per_cu) * std::max(1, cus);
+    if (hipMalloc((void**)&p->d_loops, sizeof(BatchLoop) * nloops) != hipSuccess ||
+        hipMalloc((void**)&p->d_items, sizeof(uint32_t) * items.size()) != hipSuccess ||
+        hipMemcpy(p->d_loops, p->loops.data(), sizeof(BatchLoop) * nloops, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_items, items.data(), sizeof(uint32_t) * items.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        free_plan(p);
+        return LOOP_EHIP;
+    }
+    *plan = p;
+    return LOOP_OK;
+}
+
+int loop_batch_destroy(void* plan) {
+    free_plan(static_cast<BatchPlan*>(plan));
+    return LOOP_OK;
+}
+
+int loop_batch_info(const void* plan, size_t* ws_bytes, size_t* pool_elems, long long* uhat_offsets) {
+    const BatchPlan* p = static_cast<const BatchPlan*>(plan);
+    if (!p) return LOOP_EINVAL;
+    if (ws_bytes) *ws_bytes = p->ws_bytes;
+    if (pool_elems) *pool_elems = p->pool_elems;
+    if (uhat_offsets)
+        for (int l = 0; l < p->nloops; ++l) uhat_offsets[l] = (long long)p->loops[l].uoff;
+    return LOOP_OK;
+}
+
+int loop_batch_workspace_init(const void* plan, void* ws, size_t ws_bytes, void* stream) {
+    const BatchPlan* p = static_cast<const BatchPlan*>(plan);
+    if (!p || !aligned(ws, 256)) return LOOP_EINVAL;
+    if (ws_bytes < p->ws_bytes) return LOOP_EWORKSPACE;
+    hipStream_t hs = (hipStream_t)stream;
+    char* base = static_cast<char*>(ws);
+    hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(1), 0, hs, (WsHeader*)ws);
+    hipLaunchKernelGGL(k_batch_ws_init, dim3((p->nloops + 255) / 256), dim3(256), 0, hs,
+                       reinterpret_cast<BatchQueue*>(base + p->q_off), reinterpret_cast<int*>(base + p->done_off),
+                       p->nloops);
+    return last_error();
+}
+
+int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau, int scheme, int nsteps,
+                    double* J_hist, void* ws, size_t ws_bytes, void* stream) {
+    const BatchPlan* p = static_cast<const BatchPlan*>(plan);
+    if (!p || !aligned(T, 8) || !aligned(uhat_pool, 16) || !aligned(ws, 256) || (J_hist && !aligned(J_hist, 8)))
+        return LOOP_EINVAL;
+    if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1) || nsteps < 0) return LOOP_EINVAL;
+    if (ws_bytes < p->ws_bytes) return LOOP_EWORKSPACE;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return LOOP_EHIP;
+    if (dev != p->device) return LOOP_EINVAL;
+    const cd* tw;
+    int st = get_table(&tw);
+    if (st) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    char* base = static_cast<char*>(ws);
+    cd* pool = reinterpret_cast<cd*>(uhat_pool);
+    hipLaunchKernelGGL(k_to_band_batch, dim3((p->max_nb + 31) / 32, (p->max_c + 31) / 32, p->nloops), dim3(256), 0,
+                       hs, p->d_loops, pool, base);
+    if (nsteps > 0) {
+        BatchArgs a;
+        a.loops = p->d_loops;
+        a.items = p->d_items;
+        a.nloops = p->nloops;
+        a.nA = p->nA;
+        a.ips = p->ips;
+        a.nsteps = nsteps;
+        a.q = reinterpret_cast<BatchQueue*>(base + p->q_off);
+        a.done = reinterpret_cast<int*>(base + p->done_off);
+        a.ws = base;
+        a.status = reinterpret_cast<int*>(base);
+        a.T = T;
+        a.J_hist = J_hist;
+        a.dtau = dtau;
+        a.scheme = scheme;
+        a.tw = tw;
+        const long long total = (long long)p->nA + (long long)nsteps * p->ips;
+        if (total >= (1ll << 31)) return LOOP_EINVAL;
+        hipLaunchKernelGGL(k_batch, dim3(p->grid), dim3(kBlock), p->lds_bytes, hs, a);
+    }
+    hipLaunchKernelGGL(k_from_band_batch, dim3((p->max_n + 31) / 32, (p->max_h + 31) / 32, p->nloops), dim3(256),
+                       0, hs, p->d_loops, base, pool);
     return last_error();
 }
 

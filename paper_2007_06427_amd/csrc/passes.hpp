@@ -10,6 +10,7 @@
 //                   s-transform of each retained column.
 // Pass B (rows):    u and u_x at (x_m, s_n) from inverse x-transforms of A(., s_n) and of
 //                   i q A(., s_n); w = u u_x; B(j, s_n) = forward x-transform of w, j < C.
+//                   (Each inverse transform carries two rows of one field.)
 // Pass C (columns): w_hat = forward s-transform of B, then the residual of eq. KS_R,
 //                     r_hat = -(i omega/T) u_hat - w_hat + q^2 u_hat - q^4 u_hat.
 //                   Per-column partial sums of J and dJ/dT. The linear part of the flow,
@@ -364,9 +365,12 @@ __device__ __forceinline__ cd herm_ext(const cd* tile, int TS, int r, int e, int
 // Spectrum of f + i g for two real rows f, g given by their half spectra (packed complex).
 __device__ __forceinline__ cd pack2(cd f, cd g) { return cd{f.x - g.y, f.y + g.x}; }
 
-// Inverse x-transforms of (u + i v) for rows a and b of a pair, products u v, one forward
-// x-transform of the packed products, and the split into the two rows' half spectra
-// (scaled by 1/M), written to tile[j][r] over the inputs' LDS.
+// Products of two real fields f, g on rows a and b of a pair. The two inverse x-transforms
+// take the rows of one field at a time (va = f_a + i f_b, vb = g_a + i g_b), so each transform
+// carries values of one scale; packing f and g of one row together would let the round-off
+// of the larger (r_x can exceed u by q_max^5) swamp the smaller. Then one forward transform
+// of (f_a g_a) + i (f_b g_b) and the split into the two rows' half spectra (scaled by 1/M),
+// written to tile[j][r] over the inputs' LDS.
 template <int M>
 __device__ __forceinline__ void row_products(const Shape& sh, cd* va, cd* vb, cd* lds, int t, int p,
                                              const TwCache<M, RowG<M>::PT>& twc) {
@@ -376,7 +380,7 @@ __device__ __forceinline__ void row_products(const Shape& sh, cd* va, cd* vb, cd
     fft<M, G::PT, true>(va, t, ex, twc);
     fft<M, G::PT, true>(vb, t, ex, twc);
 #pragma unroll
-    for (int m = 0; m < G::PT; ++m) va[m] = cd{va[m].x * va[m].y, vb[m].x * vb[m].y};
+    for (int m = 0; m < G::PT; ++m) va[m] = cd{va[m].x * vb[m].x, va[m].y * vb[m].y};
     fft<M, G::PT, false>(va, t, ex, twc);
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) ex[xpos(t + m * G::TPF)] = va[m];
@@ -433,10 +437,9 @@ __device__ __forceinline__ void row_pass_B(const Shape& sh, int block, const Wor
     for (int m = 0; m < G::PT; ++m) {
         const int e = t + m * G::TPF;
         const double q = dq * (double)((e <= M / 2) ? e : e - M);
-        cd a = herm_ext(lds, G::TS, p, e, M, sh.Kx);
-        va[m] = pack2(a, cd{-q * a.y, q * a.x});  // u_hat + i (i q u_hat), row a
-        a = herm_ext(lds, G::TS, G::P + p, e, M, sh.Kx);
-        vb[m] = pack2(a, cd{-q * a.y, q * a.x});  // row b
+        const cd a = herm_ext(lds, G::TS, p, e, M, sh.Kx), b = herm_ext(lds, G::TS, G::P + p, e, M, sh.Kx);
+        va[m] = pack2(a, b);                                           // u, rows a and b
+        vb[m] = pack2(cd{-q * a.y, q * a.x}, cd{-q * b.y, q * b.x});  // u_x = (i q u_hat), rows a and b
     }
     row_products<M>(sh, va, vb, lds, t, p, twc);
     store_rows<G::ROWS, G::CMAX>(lds, G::TS, w.BD, g0, sh, nrows);
@@ -502,8 +505,8 @@ __device__ __forceinline__ void row_pass_D(const Shape& sh, int block, const Wor
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) {
         const int e = t + m * G::TPF;
-        va[m] = pack2(herm_ext(tA, G::TS, p, e, M, sh.Kx), herm_ext(tC, G::TS, p, e, M, sh.Kx));
-        vb[m] = pack2(herm_ext(tA, G::TS, G::P + p, e, M, sh.Kx), herm_ext(tC, G::TS, G::P + p, e, M, sh.Kx));
+        va[m] = pack2(herm_ext(tA, G::TS, p, e, M, sh.Kx), herm_ext(tA, G::TS, G::P + p, e, M, sh.Kx));  // u
+        vb[m] = pack2(herm_ext(tC, G::TS, p, e, M, sh.Kx), herm_ext(tC, G::TS, G::P + p, e, M, sh.Kx));  // r_x
     }
     row_products<M>(sh, va, vb, lds, t, p, twc);
     store_rows<G::ROWS, G::CMAX>(lds, G::TS, w.BD, g0, sh, nrows);
