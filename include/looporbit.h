@@ -111,17 +111,38 @@ int loop_update(double L, int Nx, int Ns, int nloops, double* T, double* uhat,
  * rfft-layout pool, in the order given, at the offsets loop_batch_info reports (in complex
  * values). Periods T[nloops]; J_hist, if not NULL, is [nsteps][nloops].
  *
- * loop_batch_step queues three kernels on `stream`, and allocates and synchronises nothing:
- * a conversion into band layout (which also makes every loop canonical), the persistent
- * step kernel (all nsteps steps in one launch), and the conversion back. Its work space
+ * loop_batch_step queues its kernels on `stream`, and allocates and synchronises nothing:
+ * a conversion into band layout (which also makes every loop canonical), the steps (see
+ * loop_batch_set_schedule), and the conversion back. Its work space
  * (loop_batch_info bytes) must be prepared once by loop_batch_workspace_init. After a
  * LOOP_EHANG status, prepare it again before reuse. */
+typedef enum { LOOP_BATCH_PER_PASS = 0, LOOP_BATCH_PERSISTENT = 1 } loop_batch_schedule;
 int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns, void** plan);
+/* Choose how loop_batch_step runs the steps (results are identical bit for bit):
+ *   LOOP_BATCH_PER_PASS (default): one kernel per pass over every loop's tiles, four per step;
+ *   LOOP_BATCH_PERSISTENT: one launch for all steps, blocks pulling (pass, loop, tile) items
+ *   in dependency order (see the scheduler notes in the source). */
+int loop_batch_set_schedule(void* plan, int schedule);
 int loop_batch_destroy(void* plan);
 int loop_batch_info(const void* plan, size_t* ws_bytes, size_t* pool_elems, long long* uhat_offsets);
 int loop_batch_workspace_init(const void* plan, void* ws, size_t ws_bytes, void* stream);
 int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau, int scheme,
                     int nsteps, double* J_hist, void* ws, size_t ws_bytes, void* stream);
+
+/* The building blocks of loop_batch_step's per-pass schedule, for callers that interleave
+ * other work or time each kernel. Run loop_batch_load, then pass 0 (A) once, then passes
+ * 1..4 (B, C, D, E) for step = 0 .. nsteps-1, then loop_batch_store. This equals
+ * loop_batch_step(..., nsteps, ...) bit for bit. The pass numbering:
+ *   0 A: inverse s-transforms of the band columns;
+ *   1 B: rows, u * u_x;
+ *   2 C: columns, residual (eq. KS_R), partial J and dJ/dT, linear part of the flow;
+ *   3 D: rows, u * r_x, J and dJ/dT, period update;
+ *   4 E: columns, G_1 (eq. KS_G) and the state update, plus the next step's A unless step
+ *        is the last. */
+int loop_batch_load(const void* plan, const double* uhat_pool, void* ws, size_t ws_bytes, void* stream);
+int loop_batch_pass(const void* plan, int pass, int step, int nsteps, double* T, double dtau, int scheme,
+                    double* J_hist, void* ws, size_t ws_bytes, void* stream);
+int loop_batch_store(const void* plan, double* uhat_pool, void* ws, size_t ws_bytes, void* stream);
 
 /* Read (and clear) the sticky device status of a work space. Waits for `stream`. */
 int loop_status_sync(void* ws, void* stream);

@@ -24,8 +24,9 @@ IMEX = 1
 # every symbol include/looporbit.h declares
 EXPORTS = [
     "loop_init", "loop_shutdown", "loop_workspace_bytes", "loop_workspace_init", "loop_residual",
-    "loop_cost", "loop_adjoint_grad", "loop_step", "loop_update", "loop_batch_create", "loop_batch_destroy",
-    "loop_batch_info", "loop_batch_workspace_init", "loop_batch_step", "loop_status_sync", "loop_status_string",
+    "loop_cost", "loop_adjoint_grad", "loop_step", "loop_update", "loop_batch_create", "loop_batch_set_schedule", "loop_batch_destroy",
+    "loop_batch_info", "loop_batch_workspace_init", "loop_batch_step", "loop_batch_load", "loop_batch_pass",
+    "loop_batch_store", "loop_status_sync", "loop_status_string",
 ]
 
 
@@ -54,10 +55,14 @@ _SIGS = {
     "loop_update": ([_d, _i, _i, _i, _p, _p, _p, _p, _d, _i, _p], _i),
     "loop_batch_create": ([_i, ctypes.POINTER(_d), ctypes.POINTER(_i), ctypes.POINTER(_i),
                            ctypes.POINTER(_p)], _i),
+    "loop_batch_set_schedule": ([_p, _i], _i),
     "loop_batch_destroy": ([_p], _i),
     "loop_batch_info": ([_p, ctypes.POINTER(_sz), ctypes.POINTER(_sz), ctypes.POINTER(ctypes.c_longlong)], _i),
     "loop_batch_workspace_init": ([_p, _p, _sz, _p], _i),
     "loop_batch_step": ([_p, _p, _p, _d, _i, _i, _p, _p, _sz, _p], _i),
+    "loop_batch_load": ([_p, _p, _p, _sz, _p], _i),
+    "loop_batch_pass": ([_p, _i, _i, _i, _p, _d, _i, _p, _p, _sz, _p], _i),
+    "loop_batch_store": ([_p, _p, _p, _sz, _p], _i),
     "loop_status_sync": ([_p, _p], _i),
     "loop_status_string": ([_i], ctypes.c_char_p),
 }

@@ -177,6 +177,13 @@ class Batch:
         check(_lib.lib().loop_batch_workspace_init(plan, _ptr(self.ws), self.ws.numel(), _stream_ptr()),
               "loop_batch_workspace_init")
 
+    PER_PASS = 0
+    PERSISTENT = 1
+
+    def set_schedule(self, schedule: int):
+        """PER_PASS (four launches per step) or PERSISTENT (one launch for all steps)."""
+        check(_lib.lib().loop_batch_set_schedule(self._plan, int(schedule)), "loop_batch_set_schedule")
+
     def pack(self, spectra):
         """Pool tensor holding the given per-loop spectra (each (Ns, Nx//2+1) complex128)."""
         dev = self.ws.device
@@ -204,6 +211,20 @@ class Batch:
         check(_lib.lib().loop_batch_step(self._plan, _ptr(T), _ptr(pool), float(dtau), int(scheme), int(nsteps), jh,
                                          _ptr(self.ws), self.ws.numel(), _stream_ptr()), "loop_batch_step")
         return pool, T
+
+    def load(self, pool):
+        check(_lib.lib().loop_batch_load(self._plan, _ptr(pool), _ptr(self.ws), self.ws.numel(), _stream_ptr()),
+              "loop_batch_load")
+
+    def run_pass(self, pass_id, step, nsteps, T, dtau, scheme=EXPLICIT, J_hist=None):
+        jh = _ptr(J_hist) if J_hist is not None else None
+        check(_lib.lib().loop_batch_pass(self._plan, int(pass_id), int(step), int(nsteps), _ptr(T), float(dtau),
+                                         int(scheme), jh, _ptr(self.ws), self.ws.numel(), _stream_ptr()),
+              "loop_batch_pass")
+
+    def store(self, pool):
+        check(_lib.lib().loop_batch_store(self._plan, _ptr(pool), _ptr(self.ws), self.ws.numel(), _stream_ptr()),
+              "loop_batch_store")
 
     def status(self) -> int:
         return int(_lib.lib().loop_status_sync(_ptr(self.ws), _stream_ptr()))

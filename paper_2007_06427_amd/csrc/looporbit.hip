@@ -320,10 +320,11 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
             target = b.nt[PASS_A] + s * b.ipl;
             for (int p = PASS_B; p < pass; ++p) target += b.nt[p];
         }
+        // Thread 0's acquiring load of the counter invalidates this CU's L1 and this XCD's L2,
+        // so the block's loads after the barrier see the producers' written-back results.
         if (threadIdx.x == 0) s_stop = wait_count(&a.done[l], target, a.q, a.status);
         __syncthreads();
         if (s_stop) break;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const Work w = batch_work(b, a.ws, a.status);
         const Shape& sh = b.sh;
         switch (pass) {
@@ -345,10 +346,13 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
                 LO_COL_SWITCH(sh.N, bk_E<S_>(sh, tile, w, a.dtau, a.scheme, s + 1 < a.nsteps, lds, a.tw));
                 break;
         }
-        __threadfence();  // release this thread's results at agent scope
+        // Every wave waits until its stores have reached this XCD's L2; after the barrier one
+        // agent-scope release by thread 0 writes the L2 back, so that blocks on other XCDs
+        // can read the results, before the counter moves.
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (threadIdx.x == 0) {
-            __threadfence();  // covers the block's writes ordered before it by the barrier
+            __threadfence();
             const int need = b.nt[PASS_A] + a.nsteps * b.ipl;
             if (atomicAdd(&a.done[l], 1) + 1 == need) atomicExch(&a.done[l], 0);
         }
@@ -356,6 +360,32 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
     if (threadIdx.x == 0 && atomicAdd(&a.q->exited, 1) == (int)gridDim.x - 1) {
         atomicExch(&a.q->next, 0);
         atomicExch(&a.q->exited, 0);
+    }
+}
+
+// Launch-per-pass form of the same batched step: one kernel per pass covers the tiles of
+// every loop (block -> item code), and kernel boundaries order the passes. No counters and
+// no fences, at the cost of four launches per step.
+template <int PASS>
+__global__ __launch_bounds__(kBlock) void k_rag(BatchArgs a, const uint32_t* __restrict__ codes, int s) {
+    extern __shared__ cd lds[];
+    __shared__ double red[2 * kBlock / 64];
+    const uint32_t code = codes[blockIdx.x];
+    const int l = (int)(code >> 16), tile = (int)(code & 0x1fff);
+    const BatchLoop b = a.loops[l];
+    const Work w = batch_work(b, a.ws, a.status);
+    const Shape& sh = b.sh;
+    if constexpr (PASS == PASS_A) {
+        LO_COL_SWITCH(sh.N, col_pass_A<S_>(sh, tile, w, lds, a.tw));
+    } else if constexpr (PASS == PASS_B) {
+        LO_ROW_SWITCH(sh.M, row_pass_B<S_>(sh, tile, w, lds, a.tw));
+    } else if constexpr (PASS == PASS_C) {
+        LO_COL_SWITCH(sh.N, col_pass_C<S_>(sh, tile, a.T + l, w, MODE_STEP, a.dtau, a.scheme, lds, red, a.tw));
+    } else if constexpr (PASS == PASS_D) {
+        double* jh = a.J_hist ? a.J_hist + (size_t)s * a.nloops + l : nullptr;
+        LO_ROW_SWITCH(sh.M, row_pass_D<S_>(sh, tile, w, a.T + l, MODE_STEP, a.dtau, jh, nullptr, nullptr, lds, a.tw));
+    } else {
+        LO_COL_SWITCH(sh.N, col_pass_E<S_>(sh, tile, w, MODE_STEP, a.dtau, a.scheme, s + 1 < a.nsteps, lds, a.tw));
     }
 }
 
@@ -622,6 +652,9 @@ struct BatchPlan {
     int max_nb = 1, max_c = 1, max_n = 1, max_h = 1;
     size_t lds_bytes = 0;
     int grid = 1;
+    uint32_t* d_pass_codes = nullptr;  // all loops' tiles, pass by pass (A, B, C, D, E)
+    int pass_off[6] = {0, 0, 0, 0, 0, 0};
+    int schedule = 0;                  // LOOP_BATCH_PER_PASS or LOOP_BATCH_PERSISTENT
 };
 
 int col_tiles(const Shape& s) { return (s.C + 2048 / s.N - 1) / (2048 / s.N); }
@@ -643,6 +676,7 @@ void free_plan(BatchPlan* p) {
     if (p->device >= 0) hipSetDevice(p->device);
     if (p->d_loops) hipFree(p->d_loops);
     if (p->d_items) hipFree(p->d_items);
+    if (p->d_pass_codes) hipFree(p->d_pass_codes);
     hipSetDevice(dev0);
     delete p;
 }
@@ -851,6 +885,14 @@ int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns,
         for (int l : order)
             for (int t = 0; t < p->loops[l].nt[pass]; ++t) items.push_back(item_code(l, pass, t));
     p->ips = (int)items.size() - p->nA;
+    // per-pass code lists for the launch-per-pass schedule
+    std::vector<uint32_t> pcodes;
+    for (int pass = PASS_A; pass <= PASS_E; ++pass) {
+        p->pass_off[pass] = (int)pcodes.size();
+        for (int l : order)
+            for (int t = 0; t < p->loops[l].nt[pass]; ++t) pcodes.push_back(item_code(l, pass, t));
+    }
+    p->pass_off[5] = (int)pcodes.size();
     // one resident wave of blocks
     int per_cu = 1, cus = 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBlock, p->lds_bytes) != hipSuccess ||
@@ -862,11 +904,21 @@ int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns,
     if (hipMalloc((void**)&p->d_loops, sizeof(BatchLoop) * nloops) != hipSuccess ||
         hipMalloc((void**)&p->d_items, sizeof(uint32_t) * items.size()) != hipSuccess ||
         hipMemcpy(p->d_loops, p->loops.data(), sizeof(BatchLoop) * nloops, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_items, items.data(), sizeof(uint32_t) * items.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(p->d_items, items.data(), sizeof(uint32_t) * items.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMalloc((void**)&p->d_pass_codes, sizeof(uint32_t) * pcodes.size()) != hipSuccess ||
+        hipMemcpy(p->d_pass_codes, pcodes.data(), sizeof(uint32_t) * pcodes.size(), hipMemcpyHostToDevice) !=
+            hipSuccess) {
         free_plan(p);
         return LOOP_EHIP;
     }
     *plan = p;
+    return LOOP_OK;
+}
+
+int loop_batch_set_schedule(void* plan, int schedule) {
+    BatchPlan* p = static_cast<BatchPlan*>(plan);
+    if (!p || (schedule != LOOP_BATCH_PER_PASS && schedule != LOOP_BATCH_PERSISTENT)) return LOOP_EINVAL;
+    p->schedule = schedule;
     return LOOP_OK;
 }
 
@@ -898,48 +950,111 @@ int loop_batch_workspace_init(const void* plan, void* ws, size_t ws_bytes, void*
     return last_error();
 }
 
-int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau, int scheme, int nsteps,
-                    double* J_hist, void* ws, size_t ws_bytes, void* stream) {
-    const BatchPlan* p = static_cast<const BatchPlan*>(plan);
-    if (!p || !aligned(T, 8) || !aligned(uhat_pool, 16) || !aligned(ws, 256) || (J_hist && !aligned(J_hist, 8)))
-        return LOOP_EINVAL;
-    if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1) || nsteps < 0) return LOOP_EINVAL;
+namespace {
+int batch_check(const BatchPlan* p, const void* ws, size_t ws_bytes, const cd** tw) {
+    if (!p || !aligned(ws, 256)) return LOOP_EINVAL;
     if (ws_bytes < p->ws_bytes) return LOOP_EWORKSPACE;
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return LOOP_EHIP;
     if (dev != p->device) return LOOP_EINVAL;
+    return get_table(tw);
+}
+
+BatchArgs batch_args(const BatchPlan* p, char* base, double* T, double* J_hist, int nsteps, double dtau, int scheme,
+                     const cd* tw) {
+    BatchArgs a;
+    a.loops = p->d_loops;
+    a.items = p->d_items;
+    a.nloops = p->nloops;
+    a.nA = p->nA;
+    a.ips = p->ips;
+    a.nsteps = nsteps;
+    a.q = reinterpret_cast<BatchQueue*>(base + p->q_off);
+    a.done = reinterpret_cast<int*>(base + p->done_off);
+    a.ws = base;
+    a.status = reinterpret_cast<int*>(base);
+    a.T = T;
+    a.J_hist = J_hist;
+    a.dtau = dtau;
+    a.scheme = scheme;
+    a.tw = tw;
+    return a;
+}
+
+void launch_pass(const BatchPlan* p, int pass, int step, const BatchArgs& a, hipStream_t hs) {
+    const dim3 grid(p->pass_off[pass + 1] - p->pass_off[pass]);
+    const uint32_t* c = p->d_pass_codes + p->pass_off[pass];
+    switch (pass) {
+        case PASS_A: hipLaunchKernelGGL(k_rag<PASS_A>, grid, dim3(kBlock), p->lds_bytes, hs, a, c, step); break;
+        case PASS_B: hipLaunchKernelGGL(k_rag<PASS_B>, grid, dim3(kBlock), p->lds_bytes, hs, a, c, step); break;
+        case PASS_C: hipLaunchKernelGGL(k_rag<PASS_C>, grid, dim3(kBlock), p->lds_bytes, hs, a, c, step); break;
+        case PASS_D: hipLaunchKernelGGL(k_rag<PASS_D>, grid, dim3(kBlock), p->lds_bytes, hs, a, c, step); break;
+        default: hipLaunchKernelGGL(k_rag<PASS_E>, grid, dim3(kBlock), p->lds_bytes, hs, a, c, step); break;
+    }
+}
+}  // namespace
+
+int loop_batch_load(const void* plan, const double* uhat_pool, void* ws, size_t ws_bytes, void* stream) {
+    const BatchPlan* p = static_cast<const BatchPlan*>(plan);
     const cd* tw;
-    int st = get_table(&tw);
+    int st = batch_check(p, ws, ws_bytes, &tw);
+    if (st) return st;
+    if (!aligned(uhat_pool, 16)) return LOOP_EINVAL;
+    hipLaunchKernelGGL(k_to_band_batch, dim3((p->max_nb + 31) / 32, (p->max_c + 31) / 32, p->nloops), dim3(256), 0,
+                       (hipStream_t)stream, p->d_loops, reinterpret_cast<const cd*>(uhat_pool), static_cast<char*>(ws));
+    return last_error();
+}
+
+int loop_batch_store(const void* plan, double* uhat_pool, void* ws, size_t ws_bytes, void* stream) {
+    const BatchPlan* p = static_cast<const BatchPlan*>(plan);
+    const cd* tw;
+    int st = batch_check(p, ws, ws_bytes, &tw);
+    if (st) return st;
+    if (!aligned(uhat_pool, 16)) return LOOP_EINVAL;
+    hipLaunchKernelGGL(k_from_band_batch, dim3((p->max_n + 31) / 32, (p->max_h + 31) / 32, p->nloops), dim3(256), 0,
+                       (hipStream_t)stream, p->d_loops, static_cast<const char*>(ws), reinterpret_cast<cd*>(uhat_pool));
+    return last_error();
+}
+
+int loop_batch_pass(const void* plan, int pass, int step, int nsteps, double* T, double dtau, int scheme,
+                    double* J_hist, void* ws, size_t ws_bytes, void* stream) {
+    const BatchPlan* p = static_cast<const BatchPlan*>(plan);
+    const cd* tw;
+    int st = batch_check(p, ws, ws_bytes, &tw);
+    if (st) return st;
+    if (pass < PASS_A || pass > PASS_E || nsteps < 1 || step < 0 || step >= nsteps || !aligned(T, 8) ||
+        (J_hist && !aligned(J_hist, 8)))
+        return LOOP_EINVAL;
+    if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1)) return LOOP_EINVAL;
+    const BatchArgs a = batch_args(p, static_cast<char*>(ws), T, J_hist, nsteps, dtau, scheme, tw);
+    launch_pass(p, pass, step, a, (hipStream_t)stream);
+    return last_error();
+}
+
+int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau, int scheme, int nsteps,
+                    double* J_hist, void* ws, size_t ws_bytes, void* stream) {
+    const BatchPlan* p = static_cast<const BatchPlan*>(plan);
+    if (!p || !aligned(T, 8) || !aligned(uhat_pool, 16) || (J_hist && !aligned(J_hist, 8))) return LOOP_EINVAL;
+    if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1) || nsteps < 0) return LOOP_EINVAL;
+    const cd* tw;
+    int st = batch_check(p, ws, ws_bytes, &tw);
     if (st) return st;
     hipStream_t hs = (hipStream_t)stream;
     char* base = static_cast<char*>(ws);
-    cd* pool = reinterpret_cast<cd*>(uhat_pool);
-    hipLaunchKernelGGL(k_to_band_batch, dim3((p->max_nb + 31) / 32, (p->max_c + 31) / 32, p->nloops), dim3(256), 0,
-                       hs, p->d_loops, pool, base);
+    if ((st = loop_batch_load(plan, uhat_pool, ws, ws_bytes, stream))) return st;
     if (nsteps > 0) {
-        BatchArgs a;
-        a.loops = p->d_loops;
-        a.items = p->d_items;
-        a.nloops = p->nloops;
-        a.nA = p->nA;
-        a.ips = p->ips;
-        a.nsteps = nsteps;
-        a.q = reinterpret_cast<BatchQueue*>(base + p->q_off);
-        a.done = reinterpret_cast<int*>(base + p->done_off);
-        a.ws = base;
-        a.status = reinterpret_cast<int*>(base);
-        a.T = T;
-        a.J_hist = J_hist;
-        a.dtau = dtau;
-        a.scheme = scheme;
-        a.tw = tw;
-        const long long total = (long long)p->nA + (long long)nsteps * p->ips;
-        if (total >= (1ll << 31)) return LOOP_EINVAL;
-        hipLaunchKernelGGL(k_batch, dim3(p->grid), dim3(kBlock), p->lds_bytes, hs, a);
+        const BatchArgs a = batch_args(p, base, T, J_hist, nsteps, dtau, scheme, tw);
+        if (p->schedule == LOOP_BATCH_PERSISTENT) {
+            const long long total = (long long)p->nA + (long long)nsteps * p->ips;
+            if (total >= (1ll << 31)) return LOOP_EINVAL;
+            hipLaunchKernelGGL(k_batch, dim3(p->grid), dim3(kBlock), p->lds_bytes, hs, a);
+        } else {
+            launch_pass(p, PASS_A, 0, a, hs);
+            for (int i = 0; i < nsteps; ++i)
+                for (int pass = PASS_B; pass <= PASS_E; ++pass) launch_pass(p, pass, i, a, hs);
+        }
     }
-    hipLaunchKernelGGL(k_from_band_batch, dim3((p->max_n + 31) / 32, (p->max_h + 31) / 32, p->nloops), dim3(256),
-                       0, hs, p->d_loops, base, pool);
-    return last_error();
+    return loop_batch_store(plan, uhat_pool, ws, ws_bytes, stream);
 }
 
 int loop_status_sync(void* ws, void* stream) {

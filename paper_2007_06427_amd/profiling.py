@@ -1,0 +1,111 @@
+"""Summaries of rocprofv3 output for profiles/: per-kernel durations and HBM traffic.
+
+    python -m paper_2007_06427_amd.profiling trace <kernel_stats.csv> <out.md> <workload> "<command>"
+    python -m paper_2007_06427_amd.profiling traffic <fetch.csv> <write.csv> <workload> "<command>"
+
+`traffic` reads two counter-collection runs of the same command: FETCH_SIZE in one and
+WRITE_SIZE in the other, both in KiB per dispatch. It scales each counter by its reading for a
+plain device copy of known size. bench.py runs a 64 MiB device copy for this, so a
+calibrated counter reads 65536 KiB for that copy. It then writes
+profiles/traffic_<workload>.{json,md}, stamped with a digest of the kernel sources; bench.py
+uses the bytes only while the sources are unchanged.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+COPY_BYTES = 64 << 20
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return re.sub(r"\(.*", "", name).strip()
+
+
+def summarize_trace(stats_csv: str, out_md: str, workload: str, command: str) -> None:
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# Kernel durations: {workload}", "",
+             f"Command (run from the repository root, with `TMPDIR=/tmp`): `{command}`", "",
+             f"Kernel source digest: `{source_digest()}`", "",
+             "| kernel | calls | avg us | total ms | % of GPU time |", "|---|---:|---:|---:|---:|"]
+    for r in rows:
+        lines.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
+def _per_kernel(counter_csv: str, counter: str):
+    acc = collections.defaultdict(list)
+    grids = {}
+    for r in csv.DictReader(open(counter_csv)):
+        if r["Counter_Name"] != counter:
+            continue
+        k = short_name(r["Kernel_Name"])
+        acc[(k, r["Grid_Size"])].append(float(r["Counter_Value"]))
+        grids[(k, r["Grid_Size"])] = int(r["Grid_Size"])
+    return acc
+
+
+def summarize_traffic(fetch_csv: str, write_csv: str, workload: str, command: str) -> None:
+    fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
+    write = _per_kernel(write_csv, "WRITE_SIZE")
+    # calibration: the largest device copy is the known 64 MiB one
+    copies = [(k, v) for k, v in fetch.items() if "copyBuffer" in k[0] or "elementwise" in k[0]]
+    want_kib = COPY_BYTES / 1024
+    fcopy = max((max(v) for k, v in copies), default=None)
+    wcopies = [(k, v) for k, v in write.items() if "copyBuffer" in k[0] or "elementwise" in k[0]]
+    wcopy = max((max(v) for k, v in wcopies), default=None)
+    ffac = (fcopy / want_kib) if fcopy else 1.0
+    wfac = (wcopy / want_kib) if wcopy else 1.0
+    kernels = {}
+    for key in sorted(set(fetch) | set(write)):
+        name = key[0]
+        if not name.startswith("k_rag") and name != "k_batch":
+            continue
+        f = sum(fetch.get(key, [0.0])) / max(len(fetch.get(key, [])), 1)
+        w = sum(write.get(key, [0.0])) / max(len(write.get(key, [])), 1)
+        b = (f / ffac + w / wfac) * 1024
+        prev = kernels.get(name)
+        if prev is None or prev["dispatches"] < len(fetch.get(key, [])):
+            kernels[name] = {"fetch_kib": round(f, 1), "write_kib": round(w, 1), "bytes_per_launch": round(b),
+                             "dispatches": len(fetch.get(key, []))}
+    out = {"workload": workload, "command": command, "source_digest": source_digest(),
+           "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": fcopy, "write_kib": wcopy,
+                                "fetch_factor": ffac, "write_factor": wfac},
+           "kernels": kernels}
+    pj = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    json.dump(out, open(pj, "w"), indent=1)
+    lines = [f"# HBM traffic per dispatch: {workload}", "",
+             f"Two counter runs of: `{command}` with `--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`.", "",
+             f"Calibration: a {COPY_BYTES >> 20} MiB device copy read FETCH_SIZE {fcopy} KiB and WRITE_SIZE {wcopy} KiB "
+             f"(factors {ffac:.3f}, {wfac:.3f}); kernel readings are divided by these.", "",
+             f"Kernel source digest: `{source_digest()}`", "",
+             "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | calibrated bytes / launch |", "|---|---:|---:|---:|"]
+    for k, v in kernels.items():
+        lines.append(f"| `{k}` | {v['fetch_kib']} | {v['write_kib']} | {v['bytes_per_launch']} |")
+    open(os.path.join(ROOT, "profiles", f"traffic_{workload}.md"), "w").write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "trace":
+        summarize_trace(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+    elif sys.argv[1] == "traffic":
+        summarize_traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+    else:
+        raise SystemExit(__doc__)

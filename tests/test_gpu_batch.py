@@ -48,8 +48,12 @@ def ragged_specs(n, seed=7):
     return out
 
 
-def run_batch(api, specs, nsteps, dtau, scheme):
+SCHEDULES = [0, 1]  # per-pass launches, persistent
+
+
+def run_batch(api, specs, nsteps, dtau, scheme, schedule=0):
     b = api.Batch([(L, Nx, Ns) for (L, Nx, Ns, T, u) in specs])
+    b.set_schedule(schedule)
     pool = b.pack([torch.from_numpy(u) for (*_, u) in specs])
     T = torch.tensor([s[3] for s in specs], dtype=torch.float64, device=DEV)
     Jh = torch.zeros(max(nsteps, 1), len(specs), dtype=torch.float64, device=DEV)
@@ -59,9 +63,10 @@ def run_batch(api, specs, nsteps, dtau, scheme):
     return b, [x.cpu().numpy() for x in b.unpack(pool)], T.cpu().numpy(), Jh.cpu().numpy()
 
 
-def test_batch_matches_single_loop_steps_bitwise(api):
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_batch_matches_single_loop_steps_bitwise(api, schedule):
     specs = ragged_specs(13)
-    _, ub, Tb, Jb = run_batch(api, specs, 5, 5e-5, api.IMEX)
+    _, ub, Tb, Jb = run_batch(api, specs, 5, 5e-5, api.IMEX, schedule)
     for i, (L, Nx, Ns, T0, u0) in enumerate(specs):
         u = torch.from_numpy(u0[None]).to(DEV)
         T = torch.tensor([T0], dtype=torch.float64, device=DEV)
@@ -72,8 +77,9 @@ def test_batch_matches_single_loop_steps_bitwise(api):
         assert np.array_equal(Jh.cpu().numpy()[:, 0], Jb[:, i])
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("scheme", [0, 1])
-def test_batch_matches_oracle(api, scheme):
+def test_batch_matches_oracle(api, scheme, schedule):
     """One step from identical inputs on every loop (the per-step bar), then three steps on
     the low-mode loops of the ragged workload. Over several steps the full-band stress fields
     at Nx = 512 lose digits in the near-cancelling semi-implicit update of their band-edge
@@ -84,7 +90,7 @@ def test_batch_matches_oracle(api, scheme):
         lam_max = max(np.abs(K.lam(T, L, Nx, Ns)[K.band_mask(Nx, Ns)]).max() for (L, Nx, Ns, T, u) in specs)
         dtau = 0.5 / lam_max
     for nsteps, subset in ((1, specs), (3, specs[:6])):
-        _, ub, Tb, Jb = run_batch(api, subset, nsteps, dtau, scheme)
+        _, ub, Tb, Jb = run_batch(api, subset, nsteps, dtau, scheme, schedule)
         for i, (L, Nx, Ns, T0, u0) in enumerate(subset):
             uo, To, Jo = K.step(u0, T0, L, dtau, scheme, nsteps)
             assert wrel(ub[i], uo) < 1e-12, (nsteps, i, Nx, Ns, wrel(ub[i], uo))
@@ -92,9 +98,10 @@ def test_batch_matches_oracle(api, scheme):
             assert np.all(np.abs(Jb[:nsteps, i] - Jo) <= 1e-12 * Jo)
 
 
-def test_batch_zero_steps_canonicalises_and_relaunches(api):
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_batch_zero_steps_canonicalises_and_relaunches(api, schedule):
     specs = ragged_specs(4, seed=3)
-    b, ub, Tb, _ = run_batch(api, specs, 0, 1e-4, api.EXPLICIT)
+    b, ub, Tb, _ = run_batch(api, specs, 0, 1e-4, api.EXPLICIT, schedule)
     for i, (L, Nx, Ns, T0, u0) in enumerate(specs):
         assert np.abs(ub[i] - K.canonical(u0)).max() < 1e-16
         assert Tb[i] == T0
@@ -111,9 +118,11 @@ def test_batch_zero_steps_canonicalises_and_relaunches(api):
         assert wrel(u1[i], uo) < 1e-12
 
 
-def test_batch_graph_replay_matches_eager(api):
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_batch_graph_replay_matches_eager(api, schedule):
     specs = ragged_specs(8, seed=5)
     b = api.Batch([(L, Nx, Ns) for (L, Nx, Ns, T, u) in specs])
+    b.set_schedule(schedule)
     u0 = [torch.from_numpy(u) for (*_, u) in specs]
     T0 = torch.tensor([s[3] for s in specs], dtype=torch.float64, device=DEV)
     # eager reference: 4 launches of 2 steps
@@ -150,3 +159,23 @@ def test_batch_rejects_bad_plans(api):
         api.Batch([(22.0, 1024, 64)])  # batched row passes take Nx <= 512
     with pytest.raises(_lib.LoopOrbitError):
         api.Batch([(-1.0, 32, 64)])
+
+
+def test_pass_building_blocks_equal_batch_step(api):
+    specs = ragged_specs(9, seed=21)
+    nsteps = 3
+    b, ub, Tb, Jb = run_batch(api, specs, nsteps, 5e-5, api.IMEX)
+    pool = b.pack([torch.from_numpy(u) for (*_, u) in specs])
+    T = torch.tensor([s[3] for s in specs], dtype=torch.float64, device=DEV)
+    Jh = torch.zeros(nsteps, len(specs), dtype=torch.float64, device=DEV)
+    b.load(pool)
+    b.run_pass(0, 0, nsteps, T, 5e-5, api.IMEX, Jh)
+    for s in range(nsteps):
+        for p in (1, 2, 3, 4):
+            b.run_pass(p, s, nsteps, T, 5e-5, api.IMEX, Jh)
+    b.store(pool)
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    for i, x in enumerate(b.unpack(pool)):
+        assert np.array_equal(x.cpu().numpy(), ub[i])
+    assert np.array_equal(T.cpu().numpy(), Tb) and np.array_equal(Jh.cpu().numpy(), Jb)
