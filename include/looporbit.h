@@ -87,6 +87,17 @@ int loop_adjoint_grad(double L, int Nx, int Ns, int nloops, const double* T,
                       const double* uhat, double* Ghat, double* dJdT, double* J,
                       void* ws, size_t ws_bytes, void* stream);
 
+/* Hand-written reverse mode of J (the adjoint of Sec. 3 and App. B): the gradient of
+ * sum_l gJ[l] J_l with respect to the rfft-layout coefficients and the periods, in the
+ * complex convention grad = dJ/dRe + i dJ/dIm:
+ *   grad_uhat = -gJ[l] w_j L G_1 in the band (w_0 = 1, w_j = 2 for j >= 1), 0 elsewhere;
+ *   grad_T[l] = gJ[l] dJ/dT.
+ * gJ may be NULL (all ones). Intermediates are recomputed, not stored. grad_uhat must not
+ * alias uhat. */
+int loop_cost_grad(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat,
+                   const double* gJ, double* grad_uhat, double* grad_T, void* ws, size_t ws_bytes,
+                   void* stream);
+
 /* nsteps fictitious-time steps in place (Sec. 4.2):
  *   EXPLICIT: u_hat <- u_hat + dtau * G_1
  *   IMEX:     u_hat <- u_hat + dtau * G_1 / (1 - dtau * lambda_{j,k}(T)), the semi-implicit Euler

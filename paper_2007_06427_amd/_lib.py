@@ -24,7 +24,7 @@ IMEX = 1
 # every symbol include/looporbit.h declares
 EXPORTS = [
     "loop_init", "loop_shutdown", "loop_workspace_bytes", "loop_workspace_init", "loop_residual",
-    "loop_cost", "loop_adjoint_grad", "loop_step", "loop_update", "loop_batch_create", "loop_batch_set_schedule", "loop_batch_destroy",
+    "loop_cost", "loop_adjoint_grad", "loop_cost_grad", "loop_step", "loop_update", "loop_batch_create", "loop_batch_set_schedule", "loop_batch_destroy",
     "loop_batch_info", "loop_batch_workspace_init", "loop_batch_step", "loop_batch_load", "loop_batch_pass",
     "loop_batch_store", "loop_status_sync", "loop_status_string",
 ]
@@ -51,6 +51,7 @@ _SIGS = {
     "loop_residual": ([_d, _i, _i, _i, _p, _p, _p, _p, _sz, _p], _i),
     "loop_cost": ([_d, _i, _i, _i, _p, _p, _p, _p, _sz, _p], _i),
     "loop_adjoint_grad": ([_d, _i, _i, _i, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
+    "loop_cost_grad": ([_d, _i, _i, _i, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
     "loop_step": ([_d, _i, _i, _i, _p, _p, _d, _i, _i, _p, _p, _sz, _p], _i),
     "loop_update": ([_d, _i, _i, _i, _p, _p, _p, _p, _d, _i, _p], _i),
     "loop_batch_create": ([_i, ctypes.POINTER(_d), ctypes.POINTER(_i), ctypes.POINTER(_i),

@@ -125,6 +125,20 @@ def loop_adjoint_grad(uhat: torch.Tensor, T, L: float, ws: Workspace = None):
     return G, dJdT, J
 
 
+def loop_cost_grad(uhat: torch.Tensor, T, L: float, gJ: torch.Tensor = None, ws: Workspace = None):
+    """(grad_uhat, grad_T) of sum_l gJ[l] J_l in torch's complex convention (see the C header)."""
+    nl, Nx, Ns = shape_of(uhat)
+    T = _periods(T, nl, uhat.device)
+    if gJ is not None and (gJ.dtype != torch.float64 or gJ.numel() != nl or not gJ.is_contiguous()):
+        raise ValueError("gJ must be a contiguous float64 tensor with one entry per loop")
+    gu = torch.empty_like(uhat)
+    gT = torch.empty(nl, dtype=torch.float64, device=uhat.device)
+    ws = ws or workspace(Nx, Ns, nl)
+    check(_lib.lib().loop_cost_grad(float(L), Nx, Ns, nl, _ptr(T), _ptr(uhat), _ptr(gJ) if gJ is not None else None,
+                                    _ptr(gu), _ptr(gT), ws.ptr, ws.nbytes, _stream_ptr()), "loop_cost_grad")
+    return gu, gT
+
+
 def loop_step(uhat: torch.Tensor, T: torch.Tensor, L: float, dtau: float, scheme: int = EXPLICIT,
               nsteps: int = 1, J_hist: torch.Tensor = None, ws: Workspace = None):
     """Advance (uhat, T) in place by nsteps. J_hist, if given, is float64 (nsteps, nloops)."""

@@ -109,6 +109,43 @@ __global__ __launch_bounds__(256) void k_from_band(Shape sh, const cd* __restric
     }
 }
 
+// Gradient of sum_l gJ[l] J_l in torch's complex convention (d/dRe + i d/dIm) from G_1 in
+// band layout: grad[l][e][j] = -gJ[l] w_j L G_1, with w_0 = 1 and w_j = 2 for j >= 1. A
+// coefficient with j >= 1 stands for itself and its partner (-j, -k); column 0 holds both
+// partners. Every entry of the output is written, 0 outside the band.
+__global__ __launch_bounds__(256) void k_grad_from_band(Shape sh, const cd* __restrict__ src, const double* gJ,
+                                                        cd* __restrict__ out) {
+    __shared__ cd tile[32][33];
+    const int l = blockIdx.z, e0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+    const int tx = threadIdx.x % 32, ty0 = threadIdx.x / 32;
+    const cd* s = src + (size_t)l * sh.C * sh.NB;
+    const double g = (gJ ? gJ[l] : 1.0) * sh.L;
+    for (int ty = ty0; ty < 32; ty += 8) {
+        const int j = j0 + ty, e = e0 + tx;
+        cd v{0.0, 0.0};
+        if (j < sh.C && e < sh.N) {
+            const int kk = band_row(e, sh.N, sh.Ks);
+            if (kk >= 0) {
+                const double f = -g * (j == 0 ? 1.0 : 2.0);
+                const cd x = s[(size_t)j * sh.NB + kk];
+                v = cd{f * x.x, f * x.y};
+            }
+        }
+        tile[ty][tx] = v;
+    }
+    __syncthreads();
+    cd* o = out + (size_t)l * sh.N * sh.H;
+    for (int ty = ty0; ty < 32; ty += 8) {
+        const int e = e0 + ty, j = j0 + tx;
+        if (e < sh.N && j < sh.H) o[(size_t)e * sh.H + j] = tile[tx][ty];
+    }
+}
+
+__global__ void k_grad_T(int nloops, const double* gJ, const double* __restrict__ dJdT, double* gradT) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < nloops) gradT[l] = (gJ ? gJ[l] : 1.0) * dJdT[l];
+}
+
 // uhat <- canonical(uhat) + dtau * sigma * Hermitian-part(Ghat) in the band, 0 outside (rfft layout).
 __global__ void k_update(Shape sh, const double* __restrict__ T, cd* uhat, const cd* __restrict__ Ghat,
                          double dtau, int scheme) {
@@ -780,6 +817,29 @@ int loop_adjoint_grad(double L, int Nx, int Ns, int nloops, const double* T, con
     if ((st = launch_D(s, w, const_cast<double*>(T), MODE_GRAD, 0.0, nullptr, J, dJdT, tw, hs))) return st;
     if ((st = launch_E(s, w, MODE_GRAD, 0.0, 0, 0, tw, hs))) return st;
     launch_from_band(s, w.G, reinterpret_cast<cd*>(Ghat), hs);
+    return last_error();
+}
+
+int loop_cost_grad(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat, const double* gJ,
+                   double* grad_uhat, double* grad_T, void* ws, size_t ws_bytes, void* stream) {
+    Shape s;
+    Work w;
+    const cd* tw;
+    if (!aligned(T, 8) || !aligned(uhat, 16) || !aligned(grad_uhat, 16) || !aligned(grad_T, 8) ||
+        (gJ && !aligned(gJ, 8)) || (const void*)uhat == (const void*)grad_uhat)
+        return LOOP_EINVAL;
+    int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
+    if (st) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    launch_to_band(s, reinterpret_cast<const cd*>(uhat), w.U, hs);
+    if ((st = launch_A(s, w, tw, hs))) return st;
+    if ((st = launch_B(s, w, tw, hs))) return st;
+    if ((st = launch_C(s, T, w, MODE_GRAD, 0.0, 0, tw, hs))) return st;
+    if ((st = launch_D(s, w, const_cast<double*>(T), MODE_GRAD, 0.0, nullptr, nullptr, nullptr, tw, hs))) return st;
+    if ((st = launch_E(s, w, MODE_GRAD, 0.0, 0, 0, tw, hs))) return st;
+    dim3 grid((s.N + 31) / 32, (s.H + 31) / 32, s.nloops);
+    hipLaunchKernelGGL(k_grad_from_band, grid, dim3(256), 0, hs, s, w.G, gJ, reinterpret_cast<cd*>(grad_uhat));
+    hipLaunchKernelGGL(k_grad_T, dim3((nloops + 255) / 256), dim3(256), 0, hs, nloops, gJ, w.dJdT, grad_T);
     return last_error();
 }
 

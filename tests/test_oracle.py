@@ -316,3 +316,39 @@ def test_step_output_is_in_band_and_real():
     u, T, _ = K.step(c.uhat, c.T, c.L, 1e-4, K.EXPLICIT, 3)
     assert np.all(u[~K.band_mask(c.Nx, c.Ns)] == 0)
     assert rel(K.hermitian_column0(u), u) < 1e-14
+
+
+# ------------------------------------------------------------------------------ autograd convention
+def torch_cost(u, T, L, Nx, Ns):
+    """J = 1/2 int int r^2 written with torch.fft (CPU, FP64), differentiable in u and T."""
+    import torch
+    Kx, Ks = K.band_limits(Nx, Ns)
+    j = torch.arange(Nx // 2 + 1, dtype=torch.float64)
+    k = torch.fft.fftfreq(Ns, d=1.0 / Ns, dtype=torch.float64)
+    mask = ((k.abs()[:, None] <= Ks) & (j[None, :] <= Kx)).to(torch.complex128)
+    q = (2 * np.pi * j / L)[None, :].to(torch.complex128)
+    om = (2 * np.pi * k)[:, None].to(torch.complex128)
+    u = u * mask
+    g = lambda v: torch.fft.irfft2(v, s=(Ns, Nx), norm="forward")
+    r = -g(1j * om * u) / T - g(u) * g(1j * q * u) - g(-(q ** 2) * u) - g(q ** 4 * u)
+    r = g(torch.fft.rfft2(r, norm="forward") * mask)
+    return 0.5 * L * torch.mean(r * r)
+
+
+def test_autograd_grad_matches_torch_autograd():
+    """grad = -w_j L G_1 and dJ/dT in torch's complex convention (reading R11), against
+    torch's own autograd through torch.fft, including a non-Hermitian column 0 and
+    out-of-band entries in the input."""
+    import torch
+    rng = np.random.default_rng(RNG_SEED + 12)
+    Nx, Ns, L, T = 16, 32, 13.0, 17.0
+    u0 = loopgen.random_band_field(rng, Nx, Ns, scale=0.5)
+    u0 = u0 + 0.2 * (rng.standard_normal(u0.shape) + 1j * rng.standard_normal(u0.shape))
+    ut = torch.tensor(u0, requires_grad=True)
+    Tt = torch.tensor(T, dtype=torch.float64, requires_grad=True)
+    J = torch_cost(ut, Tt, L, Nx, Ns)
+    J.backward()
+    g_u, g_T = K.autograd_grad(u0, T, L)
+    assert abs(J.item() - K.cost(u0, T, L)) < 1e-13 * J.item()
+    assert np.max(np.abs(ut.grad.numpy() - g_u)) < 1e-12 * np.max(np.abs(g_u))
+    assert abs(Tt.grad.item() - g_T) < 1e-12 * max(abs(g_T), 1e-3 * J.item())
