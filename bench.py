@@ -29,7 +29,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 PASS_NAMES = {1: "B (rows: u u_x)", 2: "C (columns: residual, J, dJ/dT)", 3: "D (rows: u r_x, period)",
               4: "E (columns: G and update, next A)"}
-KERNEL_OF_PASS = {1: "k_rag<1>", 2: "k_rag<2>", 3: "k_rag<3>", 4: "k_rag<4>"}
 
 WORKLOADS = {
     "batched-ragged-256": 4,
@@ -111,13 +110,21 @@ def main():
     pool0 = batch.pack([torch.from_numpy(s.uhat) for s in specs])
     T0 = torch.tensor([s.T for s in specs], dtype=torch.float64, device=dev)
 
+    # ---- kernel variants and schedule chosen by the autotuner (before any timed work)
+    tuning = batch.autotune(pool0, T0, reps=20)
+    torch.cuda.synchronize()
+    variants = tuning["variants"]
+
+    def kernel_of(p):
+        return f"k_rag<{p}, {variants['ABCDE'[p]]}>"
+
     # ---- warm-up
     pool, T = pool0.clone(), T0.clone()
     batch.step(pool, T, dtau, scheme, args.warmup)
     torch.cuda.synchronize()
     assert batch.status() == 0
 
-    # ---- timed region: K steps, one loop_batch_step call (per-pass schedule)
+    # ---- timed region: K steps, one loop_batch_step call (the tuned schedule)
     pool, T = pool0.clone(), T0.clone()
     Jh = torch.zeros(steps, nl, dtype=torch.float64, device=dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -133,40 +140,49 @@ def main():
     assert np.all(np.isfinite(J))
     value = pts_step * steps / wall
 
-    # ---- per-kernel timing of the same step, pass by pass, with events on the launch stream.
-    # A backlog of queued steps keeps the GPU busy while the host enqueues the instrumented
-    # launches, so that no event pair includes host launch latency.
-    Kr = min(steps, 100)
+    # ---- per-kernel timing, pass by pass, with events on the launch stream. Every pass is a
+    # function of the work space alone, so pass p is launched R times back to back between one
+    # event pair; the launches take a negligible step (a kernel's work does not depend on it),
+    # so that pass D's repeated period updates leave T where it is. A backlog of queued whole
+    # steps goes first, so that the GPU never waits on the host inside an event pair.
+    R = 50
     step_s = wall / steps
-    pb, Tb = pool0.clone(), T0.clone()
-    batch.step(pb, Tb, dtau, scheme, max(20, int(0.05 / step_s)))
     pool, T = pool0.clone(), T0.clone()
-    batch.load(pool)
-    batch.run_pass(0, 0, Kr, T, dtau, scheme)
-    evs = {p: [] for p in (1, 2, 3, 4)}
-    for s in range(Kr):
-        for p in (1, 2, 3, 4):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            batch.run_pass(p, s, Kr, T, dtau, scheme)
-            b.record(stream)
-            evs[p].append((a, b))
-    batch.store(pool)
-    torch.cuda.synchronize()
+    nback = max(20, min(200, int(0.01 / step_s)))
+    avg_us = {}
+    for p in (1, 2, 3, 4):
+        batch.step(pool, T, dtau, scheme, nback)
+        batch.load(pool)
+        batch.run_pass(0, 0, 2, T, dtau, scheme)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(R):
+            batch.run_pass(p, 0, 2, T, 1e-30, scheme)  # step 0 of 2: E also forms the next A
+        b.record(stream)
+        torch.cuda.synchronize()
+        avg_us[p] = 1e3 * a.elapsed_time(b) / R
     assert batch.status() == 0
-    avg_us = {p: 1e3 * sum(a.elapsed_time(b) for a, b in v) / len(v) for p, v in evs.items()}
     passes_sum_us = sum(avg_us.values())
     dom = max(avg_us, key=lambda p: avg_us[p])
     by = pass_bytes(shapes, dom)
     achieved = by / (avg_us[dom] * 1e-6) / 1e9
-    traffic = measured_traffic(args.workload, KERNEL_OF_PASS[dom])
+    traffic = measured_traffic(args.workload, kernel_of(dom))
+    step_bytes = sum(pass_bytes(shapes, p) for p in (1, 2, 3, 4))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"{KERNEL_OF_PASS[dom]} pass {PASS_NAMES[dom]}", "bytes_per_launch": by,
+                "kernel": f"{kernel_of(dom)} pass {PASS_NAMES[dom]}", "bytes_per_launch": by,
                 "avg_launch_us": round(avg_us[dom], 2),
-                "passes_us": {KERNEL_OF_PASS[p]: round(v, 2) for p, v in avg_us.items()},
+                "passes_us": {kernel_of(p): round(v, 2) for p, v in avg_us.items()},
                 "passes_sum_vs_step": round(passes_sum_us / (step_s * 1e6), 3),
-                "step_bytes": sum(pass_bytes(shapes, p) for p in (1, 2, 3, 4))}
+                "step_bytes": step_bytes}
+    if tuning["schedule"] == "persistent":
+        # the timed region ran one persistent launch over all steps: that kernel is the one
+        gpu_s = e0.elapsed_time(e1) * 1e-3
+        achieved = step_bytes * steps / gpu_s / 1e9
+        roofline.update({"achieved": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic(args.workload, "k_batch"),
+                         "kernel": "k_batch (every pass of every step)", "bytes_per_launch": step_bytes * steps,
+                         "avg_launch_us": round(gpu_s * 1e6, 1)})
 
     # ---- plain method on the same loops: loop_step per loop, one after another
     plain = None
@@ -202,10 +218,12 @@ def main():
         "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "loops": nl, "shapes": sorted(set(shapes)),
-                   "scheme": cfg["scheme"], "dtau": dtau, "schedule": "per-pass launches",
+                   "scheme": cfg["scheme"], "dtau": dtau, "schedule": tuning["schedule"],
+                   "variants": variants,
                    "parallelism": "none (1 GPU)"},
         "gpu_ms_per_step": e0.elapsed_time(e1) / steps,
         "roofline": roofline, "cpu_baseline": cpu, "plain": plain,
+        "autotune": {"pass_us": tuning["pass_us"], "step_us": tuning["step_us"]},
         "batched_vs_plain": (value / plain["value"]) if plain else None,
         "J_first_last": [float(J[0].mean()), float(J[-1].mean())],
     }

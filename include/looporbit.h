@@ -155,6 +155,40 @@ int loop_batch_pass(const void* plan, int pass, int step, int nsteps, double* T,
                     double* J_hist, void* ws, size_t ws_bytes, void* stream);
 int loop_batch_store(const void* plan, double* uhat_pool, void* ws, size_t ws_bytes, void* stream);
 
+/* Kernel variants and the autotuner (per-pass schedule). Each pass has LOOP_BATCH_VARIANTS
+ * kernel variants that run the same arithmetic (results are identical bit for bit) and
+ * differ in the range of transform sizes compiled in, hence register use and wavefronts
+ * per SIMD, and, for the row passes B and D, in how tiles of rows reach LDS:
+ *   row passes:    0 sizes 8..512 staged through registers; 1 sizes 8..64 staged;
+ *                  2 sizes 8..64 copied by the load unit straight into LDS;
+ *   column passes: 0 sizes 8..1024; 1 sizes 8..64; 2 sizes 8..512.
+ * A variant is usable for a plan when its size range covers every loop's Nx (row passes)
+ * or Ns (column passes). A new plan takes the narrowest staged variant for every pass, or
+ * the configuration an earlier loop_batch_autotune chose for a plan with the same multiset
+ * of (Nx, Ns) on the same device in this process.
+ *
+ * loop_batch_set_variant: pass 0..4, variant 0..LOOP_BATCH_VARIANTS-1; LOOP_EINVAL when the
+ * variant does not cover the plan's sizes.
+ * loop_batch_get_config: any output pointer may be NULL; variants receives 5 ints.
+ *
+ * loop_batch_autotune times, on the caller's state (T[nloops], uhat_pool as for
+ * loop_batch_step; neither is modified), every usable variant of every pass over `reps`
+ * back-to-back launches (best of three trials, hipEvent timing on `stream`), keeps the
+ * fastest per pass, then times `reps` whole steps of each schedule and keeps the faster.
+ * The work of every kernel is independent of dtau and scheme, so the timing runs use a
+ * step of 1e-30 (IMEX), which leaves the state unchanged to the last bit in practice and
+ * keeps every repetition finite. It allocates temporary device copies of T and the pool,
+ * synchronises `stream`, and overwrites the work space's intermediates (the work space
+ * stays prepared). reps in [1, 1000]. report, if not NULL, receives 5 * LOOP_BATCH_VARIANTS + 2 doubles: the mean
+ * microseconds per launch of (pass, variant) at index pass * LOOP_BATCH_VARIANTS + variant
+ * (-1 for variants not usable), then microseconds per step of the per-pass and the
+ * persistent schedule. Returns a device status raised while timing, else LOOP_OK. */
+#define LOOP_BATCH_VARIANTS 3
+int loop_batch_set_variant(void* plan, int pass, int variant);
+int loop_batch_get_config(const void* plan, int* schedule, int* variants);
+int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, int reps, double* report, void* ws,
+                        size_t ws_bytes, void* stream);
+
 /* Read (and clear) the sticky device status of a work space. Waits for `stream`. */
 int loop_status_sync(void* ws, void* stream);
 

@@ -26,7 +26,8 @@ EXPORTS = [
     "loop_init", "loop_shutdown", "loop_workspace_bytes", "loop_workspace_init", "loop_residual",
     "loop_cost", "loop_adjoint_grad", "loop_cost_grad", "loop_step", "loop_update", "loop_batch_create", "loop_batch_set_schedule", "loop_batch_destroy",
     "loop_batch_info", "loop_batch_workspace_init", "loop_batch_step", "loop_batch_load", "loop_batch_pass",
-    "loop_batch_store", "loop_status_sync", "loop_status_string",
+    "loop_batch_store", "loop_batch_set_variant", "loop_batch_get_config", "loop_batch_autotune",
+    "loop_status_sync", "loop_status_string",
 ]
 
 
@@ -64,6 +65,9 @@ _SIGS = {
     "loop_batch_load": ([_p, _p, _p, _sz, _p], _i),
     "loop_batch_pass": ([_p, _i, _i, _i, _p, _d, _i, _p, _p, _sz, _p], _i),
     "loop_batch_store": ([_p, _p, _p, _sz, _p], _i),
+    "loop_batch_set_variant": ([_p, _i, _i], _i),
+    "loop_batch_get_config": ([_p, ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
+    "loop_batch_autotune": ([_p, _p, _p, _i, ctypes.POINTER(_d), _p, _sz, _p], _i),
     "loop_status_sync": ([_p, _p], _i),
     "loop_status_string": ([_i], ctypes.c_char_p),
 }

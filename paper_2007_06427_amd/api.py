@@ -198,6 +198,46 @@ class Batch:
         """PER_PASS (four launches per step) or PERSISTENT (one launch for all steps)."""
         check(_lib.lib().loop_batch_set_schedule(self._plan, int(schedule)), "loop_batch_set_schedule")
 
+    VARIANTS = 3
+    PASS_NAMES = ("A", "B", "C", "D", "E")
+
+    def set_variant(self, pass_id: int, variant: int):
+        """Kernel variant of one pass of the per-pass schedule (see loop_batch_set_variant)."""
+        check(_lib.lib().loop_batch_set_variant(self._plan, int(pass_id), int(variant)), "loop_batch_set_variant")
+
+    def config(self) -> dict:
+        """The schedule and the kernel variant of each pass currently in use."""
+        sc = ctypes.c_int(0)
+        v = (ctypes.c_int * 5)()
+        check(_lib.lib().loop_batch_get_config(self._plan, ctypes.byref(sc), v), "loop_batch_get_config")
+        return {"schedule": "persistent" if sc.value == self.PERSISTENT else "per-pass",
+                "variants": {n: int(v[i]) for i, n in enumerate(self.PASS_NAMES)}}
+
+    def autotune(self, pool, T, reps=20) -> dict:
+        """Time every usable kernel variant of every pass and both schedules on this state
+        (pool and T are left unchanged) and keep the fastest (see loop_batch_autotune).
+        Returns the timings in microseconds and the chosen configuration."""
+        self._check_state(pool, T)
+        n = 5 * self.VARIANTS + 2
+        rep = (ctypes.c_double * n)()
+        check(_lib.lib().loop_batch_autotune(self._plan, _ptr(T), _ptr(pool), int(reps), rep, _ptr(self.ws),
+                                             self.ws.numel(), _stream_ptr()),
+              "loop_batch_autotune")
+        passes = {}
+        for i, name in enumerate(self.PASS_NAMES):
+            passes[name] = {v: round(rep[i * self.VARIANTS + v], 3) for v in range(self.VARIANTS)
+                            if rep[i * self.VARIANTS + v] >= 0}
+        out = self.config()
+        out["pass_us"] = passes
+        out["step_us"] = {"per-pass": round(rep[n - 2], 3), "persistent": round(rep[n - 1], 3)}
+        return out
+
+    def _check_state(self, pool, T):
+        if pool.dtype != torch.complex128 or pool.numel() != self.pool_elems or not pool.is_contiguous():
+            raise ValueError("pool must be the contiguous complex128 pool of this plan")
+        if T.dtype != torch.float64 or T.numel() != self.nloops or not T.is_contiguous():
+            raise ValueError("T must be float64 with one entry per loop")
+
     def pack(self, spectra):
         """Pool tensor holding the given per-loop spectra (each (Ns, Nx//2+1) complex128)."""
         dev = self.ws.device
@@ -215,10 +255,7 @@ class Batch:
                 for (L, Nx, Ns), off in zip(self.shapes, self.offsets)]
 
     def step(self, pool, T, dtau, scheme=EXPLICIT, nsteps=1, J_hist=None):
-        if pool.dtype != torch.complex128 or pool.numel() != self.pool_elems or not pool.is_contiguous():
-            raise ValueError("pool must be the contiguous complex128 pool of this plan")
-        if T.dtype != torch.float64 or T.numel() != self.nloops or not T.is_contiguous():
-            raise ValueError("T must be float64 with one entry per loop")
+        self._check_state(pool, T)
         if J_hist is not None and (J_hist.dtype != torch.float64 or J_hist.numel() < nsteps * self.nloops):
             raise ValueError("J_hist must be float64 (nsteps, nloops)")
         jh = _ptr(J_hist) if J_hist is not None else None

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "looporbit.h"
@@ -403,8 +404,44 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
 // Launch-per-pass form of the same batched step: one kernel per pass covers the tiles of
 // every loop (block -> item code), and kernel boundaries order the passes. No counters and
 // no fences, at the cost of four launches per step.
-template <int PASS>
+//
+// Each pass has a few kernel variants, k_rag<PASS, V>. A variant fixes the range of
+// transform sizes its size dispatch contains. Registers are allocated for the largest body
+// a kernel holds, so a kernel limited to short transforms can keep more wavefronts per SIMD.
+// For the row passes a variant also fixes how a tile of rows reaches LDS: staged through
+// vector registers (load_rows) or copied by the load unit (load_rows_lds). Every variant
+// runs the same arithmetic; a plan starts with the narrowest staged variant that covers its
+// sizes, and loop_batch_autotune times the others.
+struct RagVariant {
+    int lo, hi;  // transform sizes compiled in: powers of two in [lo, hi]
+    bool dma;    // row tiles copied straight into LDS
+};
+constexpr int kRagVariants = 3;
+__host__ __device__ constexpr bool is_row_pass(int pass) { return pass == PASS_B || pass == PASS_D; }
+__host__ __device__ constexpr RagVariant rag_variant(int pass, int v) {
+    return is_row_pass(pass) ? (v == 0   ? RagVariant{8, 512, false}
+                                : v == 1 ? RagVariant{8, 64, false}
+                                         : RagVariant{8, 64, true})
+                             : (v == 0   ? RagVariant{8, 1024, false}
+                                : v == 1 ? RagVariant{8, 64, false}
+                                         : RagVariant{8, 512, false});
+}
+
+// Calls f(std::integral_constant<int, S>) for the power of two S == n in [LO, HI]; other n do
+// nothing (plans only hold sizes their kernels cover).
+template <int LO, int HI, class F>
+__device__ __forceinline__ void size_switch(int n, F&& f) {
+    if constexpr (LO <= HI) {
+        if (n == LO)
+            f(std::integral_constant<int, LO>{});
+        else
+            size_switch<2 * LO, HI>(n, static_cast<F&&>(f));
+    }
+}
+
+template <int PASS, int V>
 __global__ __launch_bounds__(kBlock) void k_rag(BatchArgs a, const uint32_t* __restrict__ codes, int s) {
+    constexpr RagVariant var = rag_variant(PASS, V);
     extern __shared__ cd lds[];
     __shared__ double red[2 * kBlock / 64];
     const uint32_t code = codes[blockIdx.x];
@@ -413,16 +450,33 @@ __global__ __launch_bounds__(kBlock) void k_rag(BatchArgs a, const uint32_t* __r
     const Work w = batch_work(b, a.ws, a.status);
     const Shape& sh = b.sh;
     if constexpr (PASS == PASS_A) {
-        LO_COL_SWITCH(sh.N, col_pass_A<S_>(sh, tile, w, lds, a.tw));
+        size_switch<var.lo, var.hi>(sh.N, [&](auto c) { col_pass_A<decltype(c)::value>(sh, tile, w, lds, a.tw); });
     } else if constexpr (PASS == PASS_B) {
-        LO_ROW_SWITCH(sh.M, row_pass_B<S_>(sh, tile, w, lds, a.tw));
+        size_switch<var.lo, var.hi>(
+            sh.M, [&](auto c) { row_pass_B<decltype(c)::value, var.dma>(sh, tile, w, lds, a.tw); });
     } else if constexpr (PASS == PASS_C) {
-        LO_COL_SWITCH(sh.N, col_pass_C<S_>(sh, tile, a.T + l, w, MODE_STEP, a.dtau, a.scheme, lds, red, a.tw));
+        size_switch<var.lo, var.hi>(sh.N, [&](auto c) {
+            col_pass_C<decltype(c)::value>(sh, tile, a.T + l, w, MODE_STEP, a.dtau, a.scheme, lds, red, a.tw);
+        });
     } else if constexpr (PASS == PASS_D) {
         double* jh = a.J_hist ? a.J_hist + (size_t)s * a.nloops + l : nullptr;
-        LO_ROW_SWITCH(sh.M, row_pass_D<S_>(sh, tile, w, a.T + l, MODE_STEP, a.dtau, jh, nullptr, nullptr, lds, a.tw));
+        size_switch<var.lo, var.hi>(sh.M, [&](auto c) {
+            row_pass_D<decltype(c)::value, var.dma>(sh, tile, w, a.T + l, MODE_STEP, a.dtau, jh, nullptr, nullptr,
+                                                    lds, a.tw);
+        });
     } else {
-        LO_COL_SWITCH(sh.N, col_pass_E<S_>(sh, tile, w, MODE_STEP, a.dtau, a.scheme, s + 1 < a.nsteps, lds, a.tw));
+        size_switch<var.lo, var.hi>(sh.N, [&](auto c) {
+            col_pass_E<decltype(c)::value>(sh, tile, w, MODE_STEP, a.dtau, a.scheme, s + 1 < a.nsteps, lds, a.tw);
+        });
+    }
+}
+
+template <int PASS>
+void launch_rag(int v, dim3 grid, size_t lds, hipStream_t hs, const BatchArgs& a, const uint32_t* c, int step) {
+    switch (v) {
+        case 0: hipLaunchKernelGGL((k_rag<PASS, 0>), grid, dim3(kBlock), lds, hs, a, c, step); break;
+        case 1: hipLaunchKernelGGL((k_rag<PASS, 1>), grid, dim3(kBlock), lds, hs, a, c, step); break;
+        default: hipLaunchKernelGGL((k_rag<PASS, 2>), grid, dim3(kBlock), lds, hs, a, c, step); break;
     }
 }
 
@@ -692,6 +746,9 @@ struct BatchPlan {
     uint32_t* d_pass_codes = nullptr;  // all loops' tiles, pass by pass (A, B, C, D, E)
     int pass_off[6] = {0, 0, 0, 0, 0, 0};
     int schedule = 0;                  // LOOP_BATCH_PER_PASS or LOOP_BATCH_PERSISTENT
+    int variant[5] = {0, 0, 0, 0, 0};  // k_rag variant of each pass
+    size_t pass_lds[5] = {0, 0, 0, 0, 0};  // dynamic LDS of each pass's launches
+    int min_m = 1 << 30, max_m = 0, min_n = 1 << 30, max_n2 = 0;  // transform sizes present
 };
 
 int col_tiles(const Shape& s) { return (s.C + 2048 / s.N - 1) / (2048 / s.N); }
@@ -704,6 +761,44 @@ size_t pass_lds_bytes(const Shape& s) {
     const int rows = 4096 / s.M, cmax = (s.M - 1) / 3 + 1;
     const size_t row = std::max<size_t>(2 * (size_t)cmax * (rows + 1), 2304);
     return std::max(col, row) * sizeof(cd);
+}
+template <int LO, int HI, class F>
+void host_size_switch(int n, F&& f) {
+    if constexpr (LO <= HI) {
+        if (n == LO)
+            f(std::integral_constant<int, LO>{});
+        else
+            host_size_switch<2 * LO, HI>(n, static_cast<F&&>(f));
+    }
+}
+// Dynamic LDS of one pass of the launch-per-pass form for a loop of this shape.
+size_t rag_lds_bytes(const Shape& s, int pass) {
+    size_t n = 0;
+    auto row = [&](auto c) {
+        using G = RowG<decltype(c)::value>;
+        n = pass == PASS_B ? G::LDS_B : G::LDS;
+    };
+    auto col = [&](auto c) { n = ColG<decltype(c)::value>::LDS; };
+    if (is_row_pass(pass))
+        host_size_switch<8, 512>(s.M, row);
+    else
+        host_size_switch<8, 1024>(s.N, col);
+    return n * sizeof(cd);
+}
+bool rag_covers(const BatchPlan* p, int pass, int v) {
+    if (v < 0 || v >= kRagVariants) return false;
+    const RagVariant r = rag_variant(pass, v);
+    const int lo = is_row_pass(pass) ? p->min_m : p->min_n, hi = is_row_pass(pass) ? p->max_m : p->max_n2;
+    return r.lo <= lo && hi <= r.hi;
+}
+// The narrowest staged variant covering the plan's sizes.
+int rag_default(const BatchPlan* p, int pass) {
+    int best = 0;
+    for (int v = 0; v < kRagVariants; ++v) {
+        const RagVariant r = rag_variant(pass, v), b = rag_variant(pass, best);
+        if (!r.dma && rag_covers(p, pass, v) && r.hi - r.lo < b.hi - b.lo) best = v;
+    }
+    return best;
 }
 
 void free_plan(BatchPlan* p) {
@@ -729,6 +824,29 @@ int last_error() { return hipGetLastError() == hipSuccess ? LOOP_OK : LOOP_EHIP;
 }  // namespace
 
 // ============================================================================ C ABI
+// Configurations chosen by loop_batch_autotune, per device and multiset of (Nx, Ns), for
+// the plans created later in the process.
+struct TunedConfig {
+    int schedule;
+    int variant[5];
+};
+std::mutex g_tune_mu;
+std::map<std::vector<int>, TunedConfig>& tune_cache() {
+    static std::map<std::vector<int>, TunedConfig> m;
+    return m;
+}
+std::vector<int> plan_signature(const BatchPlan* p) {
+    std::vector<std::pair<int, int>> sh;
+    for (const BatchLoop& b : p->loops) sh.emplace_back(b.sh.M, b.sh.N);
+    std::sort(sh.begin(), sh.end());
+    std::vector<int> key{p->device};
+    for (const auto& x : sh) {
+        key.push_back(x.first);
+        key.push_back(x.second);
+    }
+    return key;
+}
+
 extern "C" {
 
 int loop_init(void) {
@@ -928,6 +1046,21 @@ int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns,
         p->max_n = std::max(p->max_n, b.sh.N);
         p->max_h = std::max(p->max_h, b.sh.H);
         p->lds_bytes = std::max(p->lds_bytes, pass_lds_bytes(b.sh));
+        for (int pass = PASS_A; pass <= PASS_E; ++pass)
+            p->pass_lds[pass] = std::max(p->pass_lds[pass], rag_lds_bytes(b.sh, pass));
+        p->min_m = std::min(p->min_m, b.sh.M);
+        p->max_m = std::max(p->max_m, b.sh.M);
+        p->min_n = std::min(p->min_n, b.sh.N);
+        p->max_n2 = std::max(p->max_n2, b.sh.N);
+    }
+    for (int pass = PASS_A; pass <= PASS_E; ++pass) p->variant[pass] = rag_default(p, pass);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        const auto it = tune_cache().find(plan_signature(p));
+        if (it != tune_cache().end()) {
+            p->schedule = it->second.schedule;
+            for (int pass = PASS_A; pass <= PASS_E; ++pass) p->variant[pass] = it->second.variant[pass];
+        }
     }
     p->ws_bytes = off;
     p->pool_elems = pool;
@@ -1044,12 +1177,14 @@ BatchArgs batch_args(const BatchPlan* p, char* base, double* T, double* J_hist, 
 void launch_pass(const BatchPlan* p, int pass, int step, const BatchArgs& a, hipStream_t hs) {
     const dim3 grid(p->pass_off[pass + 1] - p->pass_off[pass]);
     const uint32_t* c = p->d_pass_codes + p->pass_off[pass];
+    const int v = p->variant[pass];
+    const size_t lds = p->pass_lds[pass];
     switch (pass) {
-        case PASS_A: hipLaunchKernelGGL(k_rag<PASS_A>, grid, dim3(kBlock), p->lds_bytes, hs, a, c, step); break;
-        case PASS_B: hipLaunchKernelGGL(k_rag<PASS_B>, grid, dim3(kBlock), p->lds_bytes, hs, a, c, step); break;
-        case PASS_C: hipLaunchKernelGGL(k_rag<PASS_C>, grid, dim3(kBlock), p->lds_bytes, hs, a, c, step); break;
-        case PASS_D: hipLaunchKernelGGL(k_rag<PASS_D>, grid, dim3(kBlock), p->lds_bytes, hs, a, c, step); break;
-        default: hipLaunchKernelGGL(k_rag<PASS_E>, grid, dim3(kBlock), p->lds_bytes, hs, a, c, step); break;
+        case PASS_A: launch_rag<PASS_A>(v, grid, lds, hs, a, c, step); break;
+        case PASS_B: launch_rag<PASS_B>(v, grid, lds, hs, a, c, step); break;
+        case PASS_C: launch_rag<PASS_C>(v, grid, lds, hs, a, c, step); break;
+        case PASS_D: launch_rag<PASS_D>(v, grid, lds, hs, a, c, step); break;
+        default: launch_rag<PASS_E>(v, grid, lds, hs, a, c, step); break;
     }
 }
 }  // namespace
@@ -1115,6 +1250,113 @@ int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau,
         }
     }
     return loop_batch_store(plan, uhat_pool, ws, ws_bytes, stream);
+}
+
+int loop_batch_set_variant(void* plan, int pass, int variant) {
+    BatchPlan* p = static_cast<BatchPlan*>(plan);
+    if (!p || pass < PASS_A || pass > PASS_E || !rag_covers(p, pass, variant)) return LOOP_EINVAL;
+    p->variant[pass] = variant;
+    return LOOP_OK;
+}
+
+int loop_batch_get_config(const void* plan, int* schedule, int* variants) {
+    const BatchPlan* p = static_cast<const BatchPlan*>(plan);
+    if (!p) return LOOP_EINVAL;
+    if (schedule) *schedule = p->schedule;
+    if (variants)
+        for (int pass = PASS_A; pass <= PASS_E; ++pass) variants[pass] = p->variant[pass];
+    return LOOP_OK;
+}
+
+int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, int reps, double* report, void* ws,
+                        size_t ws_bytes, void* stream) {
+    BatchPlan* p = static_cast<BatchPlan*>(plan);
+    if (!p || !aligned(T, 8) || !aligned(uhat_pool, 16) || reps < 1 || reps > 1000) return LOOP_EINVAL;
+    // The kernels' work does not depend on the step size or the scheme, so the timing runs
+    // take a step too small to move the state: repeated passes and steps stay finite.
+    const double dtau = 1e-30;
+    const int scheme = LOOP_EULER_IMEX;
+    const cd* tw;
+    int st = batch_check(p, ws, ws_bytes, &tw);
+    if (st) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    char* base = static_cast<char*>(ws);
+    double* tT = nullptr;
+    double* tpool = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto release = [&]() {
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+        if (tT) hipFree(tT);
+        if (tpool) hipFree(tpool);
+    };
+    const size_t pool_bytes = sizeof(cd) * p->pool_elems;
+    if (hipMalloc((void**)&tT, sizeof(double) * p->nloops) != hipSuccess ||
+        hipMalloc((void**)&tpool, pool_bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess ||
+        hipMemcpyAsync(tT, T, sizeof(double) * p->nloops, hipMemcpyDeviceToDevice, hs) != hipSuccess ||
+        hipMemcpyAsync(tpool, uhat_pool, pool_bytes, hipMemcpyDeviceToDevice, hs) != hipSuccess) {
+        release();
+        return LOOP_EHIP;
+    }
+    std::vector<double> rep(5 * kRagVariants + 2, -1.0);
+    // Mean microseconds per call of `launch` over n back-to-back calls, best of three trials.
+    auto time_calls = [&](auto&& launch, int n) -> double {
+        double best = 1e300;
+        for (int trial = 0; trial < 3; ++trial) {
+            hipEventRecord(e0, hs);
+            for (int i = 0; i < n; ++i) launch();
+            hipEventRecord(e1, hs);
+            hipEventSynchronize(e1);
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            best = std::min(best, 1e3 * (double)ms / n);
+        }
+        return best;
+    };
+    // Every pass is a function of the work space alone (pass D also moves the copy of T), so
+    // after one full step each pass can be repeated in place and timed.
+    loop_batch_load(p, tpool, ws, ws_bytes, stream);
+    const BatchArgs a = batch_args(p, base, tT, nullptr, 2, dtau, scheme, tw);
+    for (int pass = PASS_A; pass <= PASS_E; ++pass) launch_pass(p, pass, 0, a, hs);
+    for (int pass = PASS_A; pass <= PASS_E; ++pass) {
+        int best_v = p->variant[pass];
+        double best_t = 1e300;
+        for (int v = 0; v < kRagVariants; ++v) {
+            if (!rag_covers(p, pass, v)) continue;
+            p->variant[pass] = v;
+            launch_pass(p, pass, 0, a, hs);  // the first launch of a kernel also loads its code
+            const double t = time_calls([&] { launch_pass(p, pass, 0, a, hs); }, reps);
+            rep[pass * kRagVariants + v] = t;
+            if (t < best_t) {
+                best_t = t;
+                best_v = v;
+            }
+        }
+        p->variant[pass] = best_v;
+    }
+    double sched_us[2];
+    for (int sc = LOOP_BATCH_PER_PASS; sc <= LOOP_BATCH_PERSISTENT; ++sc) {
+        p->schedule = sc;
+        loop_batch_step(p, tT, tpool, dtau, scheme, 1, nullptr, ws, ws_bytes, stream);
+        sched_us[sc] = time_calls([&] { loop_batch_step(p, tT, tpool, dtau, scheme, reps, nullptr, ws, ws_bytes, stream); }, 1) / reps;
+        rep[5 * kRagVariants + sc] = sched_us[sc];
+    }
+    p->schedule = sched_us[LOOP_BATCH_PERSISTENT] < sched_us[LOOP_BATCH_PER_PASS] ? LOOP_BATCH_PERSISTENT
+                                                                                 : LOOP_BATCH_PER_PASS;
+    st = last_error();
+    if (hipStreamSynchronize(hs) != hipSuccess) st = LOOP_EHIP;
+    release();
+    if (st) return st;
+    st = loop_status_sync(ws, stream);
+    if (st) return st;
+    if (report) std::copy(rep.begin(), rep.end(), report);
+    TunedConfig c;
+    c.schedule = p->schedule;
+    for (int pass = PASS_A; pass <= PASS_E; ++pass) c.variant[pass] = p->variant[pass];
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_cache()[plan_signature(p)] = c;
+    return LOOP_OK;
 }
 
 int loop_status_sync(void* ws, void* stream) {

@@ -304,6 +304,7 @@ struct RowG {
     static constexpr int XL = P * xlen<M>();
     // LDS: two input tiles, aliased afterwards by the exchange regions and the output tile
     static constexpr int LDS = (2 * TILE > XL ? 2 * TILE : XL);
+    static constexpr int LDS_B = (TILE > XL ? TILE : XL);  // pass B holds one input tile
     static constexpr int PW = 64 / TPF;                   // pairs per wavefront
     static constexpr int NOUT = (2 * PW * CMAX + 63) / 64;  // split outputs per thread
 };
@@ -337,6 +338,37 @@ __device__ __forceinline__ void load_rows(cd* tile, const cd* const (&X)[NT], si
             for (int q = 0; q < NT; ++q) tile[q * TILE + j * TS + r] = buf[q][k];
         }
     }
+}
+
+// The same tiles as load_rows, copied by the load unit straight into LDS
+// (global_load_lds_dwordx4: lane i of a wavefront writes 16 bytes at the instruction's LDS
+// base + 16 i). One wavefront instruction moves 64 consecutive rows of one column j to
+// tile[j][r0 .. r0 + 63], so ROWS must be a multiple of 64. Nothing passes through vector
+// registers. Lanes whose row lies past nrows store zeros with ordinary LDS writes instead.
+// The wavefront waits for its own copies before returning; the caller's barrier then makes
+// every wavefront's copies visible to the block.
+template <int ROWS, int CMAX, int TS, int TILE, int NT>
+__device__ __forceinline__ void load_rows_lds(cd* tile, const cd* const (&X)[NT], size_t g0, const Shape& sh,
+                                              size_t nrows) {
+    static_assert(ROWS % 64 == 0, "a copy instruction covers 64 rows of one column");
+    constexpr int RC = ROWS / 64;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int per_field = sh.C * RC;
+    const size_t g = g0 + lane;
+    for (int k = wave; k < NT * per_field; k += kBlock / 64) {
+        const int q = k / per_field, rem = k % per_field;
+        const int j = rem / RC, r0 = (rem % RC) * 64;
+        cd* dst = tile + q * TILE + j * TS + r0;
+        const size_t gr = g + r0;
+        if (gr < nrows) {
+            const cd* src = X[q] + ((gr >> sh.logN) * sh.C + j) * sh.N + (gr & (size_t)(sh.N - 1));
+            __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)const_cast<cd*>(src),
+                                             (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+        } else {
+            dst[lane] = cd{0.0, 0.0};
+        }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
 template <int ROWS, int CMAX>
@@ -417,7 +449,8 @@ __device__ __forceinline__ void row_products(const Shape& sh, cd* va, cd* vb, cd
     __syncthreads();
 }
 
-template <int M>
+// DMA selects load_rows_lds over load_rows (tiles of 64 rows or more).
+template <int M, bool DMA = false>
 __device__ __forceinline__ void row_pass_B(const Shape& sh, int block, const Work& w, cd* lds,
                                            const cd* __restrict__ tw) {
     using G = RowG<M>;
@@ -428,7 +461,10 @@ __device__ __forceinline__ void row_pass_B(const Shape& sh, int block, const Wor
     tw_cache_load<M, G::PT>(twc, t, tw);
     {
         const cd* const src[1] = {w.A};
-        load_rows<G::ROWS, G::CMAX, G::TS, G::TILE, 1>(lds, src, g0, sh, nrows);
+        if constexpr (DMA)
+            load_rows_lds<G::ROWS, G::CMAX, G::TS, G::TILE, 1>(lds, src, g0, sh, nrows);
+        else
+            load_rows<G::ROWS, G::CMAX, G::TS, G::TILE, 1>(lds, src, g0, sh, nrows);
     }
     __syncthreads();
     const double dq = kTwoPi / sh.L;
@@ -478,7 +514,7 @@ __device__ __forceinline__ void finalize_loop(const Shape& sh, int l, const Work
     if (bad) atomicCAS(w.status, 0, -4);
 }
 
-template <int M>
+template <int M, bool DMA = false>
 __device__ __forceinline__ void row_pass_D(const Shape& sh, int block, const Work& w, double* T, int mode,
                                            double dtau, double* J_hist, double* Jout, double* dJdTout, cd* lds,
                                            const cd* __restrict__ tw) {
@@ -498,7 +534,10 @@ __device__ __forceinline__ void row_pass_D(const Shape& sh, int block, const Wor
     tw_cache_load<M, G::PT>(twc, t, tw);
     {
         const cd* const src[2] = {w.A, w.Cb};
-        load_rows<G::ROWS, G::CMAX, G::TS, G::TILE, 2>(tA, src, g0, sh, nrows);
+        if constexpr (DMA)
+            load_rows_lds<G::ROWS, G::CMAX, G::TS, G::TILE, 2>(tA, src, g0, sh, nrows);
+        else
+            load_rows<G::ROWS, G::CMAX, G::TS, G::TILE, 2>(tA, src, g0, sh, nrows);
     }
     __syncthreads();
     cd va[G::PT], vb[G::PT];
