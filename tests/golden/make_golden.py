@@ -37,6 +37,33 @@ def trajectory(c, steps, scheme, dtau, marks):
     }
 
 
+def converged(c, dtau, scheme, jtol, chunk):
+    """Run the oracle from workload c's seed, chunk steps at a time, until J < jtol at a chunk
+    end. Records the step count, the end state's period, cost, band-mode magnitudes (which an
+    x- or s-shift leaves alone) and how far the end state is from time independence."""
+    spec = loopgen.config_loops(c)[0]
+    u, T = spec.uhat, spec.T
+    n = 0
+    while True:
+        u, T, _ = K.step(u, T, spec.L, dtau, scheme, chunk)
+        n += chunk
+        J = K.cost(u, T, spec.L)
+        if J < jtol:
+            break
+    uc = K.canonical(u)
+    norm_u = float(np.sqrt(K.inner(uc, uc, spec.L)))
+    us = K.d_s(uc, spec.L)
+    norm_us = float(np.sqrt(K.inner(us, us, spec.L)))
+    kind = "equilibrium" if norm_us < 1e-3 * norm_u else ("trivial" if norm_u < 1e-6 else "periodic orbit")
+    return {
+        "workload": loopgen.CONFIGS[c]["name"], "seed": spec.seed, "L": spec.L, "Nx": spec.Nx, "Ns": spec.Ns,
+        "T0": spec.T, "dtau": dtau, "scheme": "imex" if scheme == K.IMEX else "explicit", "J_tol": jtol,
+        "steps": n, "T_final": float(T), "J_final": float(J), "norm_u": norm_u, "norm_u_s": norm_us,
+        "end_state": kind, "abs_uhat_final_band": [[j, k, abs(complex(re, im))]
+                                                   for j, k, re, im in band_list(u, spec.Nx, spec.Ns)],
+    }
+
+
 def main():
     data = trajectory(1, 2000, K.EXPLICIT, 1e-4, [0, 1, 10, 100, 1000, 1999])
     with open(os.path.join(HERE, "oracle_traj_plain32x32.json"), "w") as f:
@@ -44,6 +71,9 @@ def main():
     data = trajectory(2, 200, K.IMEX, 5e-5, [0, 1, 10, 100, 199])
     data.pop("uhat_final_band")
     with open(os.path.join(HERE, "oracle_traj_plain64x128_200.json"), "w") as f:
+        json.dump(data, f, indent=1)
+    data = converged(1, 0.05, K.IMEX, 1e-10, 2000)
+    with open(os.path.join(HERE, "oracle_converged_plain32x32.json"), "w") as f:
         json.dump(data, f, indent=1)
 
 

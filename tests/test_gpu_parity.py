@@ -242,3 +242,24 @@ def test_trajectory_plain64x128_imex(api):
         assert abs(Jh[int(m)] - v) <= 1e-10 * v
     assert abs(Td.item() - g["T_final"]) <= 1e-10 * g["T_final"]
     assert np.all(np.diff(Jh) <= 0)
+
+
+def test_reaches_the_oracle_converged_state(api):
+    """Convergence parity: from the 32 x 32 workload's seed, IMEX at dtau = 0.05, the oracle
+    needed the stored number of steps to bring J below 1e-10 (it ends on an equilibrium).
+    The GPU run of the same steps must end with J < 1e-10, T within 1e-8 of the oracle's,
+    and the same band-mode magnitudes (invariant under the x- and s-shifts that leave J
+    unchanged) to 1e-8."""
+    g = json.load(open(os.path.join(HERE, "oracle_converged_plain32x32.json")))
+    spec = loopgen.config_loops(1)[0]
+    assert (spec.Nx, spec.Ns, spec.L, spec.T) == (g["Nx"], g["Ns"], g["L"], g["T0"])
+    ud, Td = to_dev(spec.uhat[None], np.array([spec.T]))
+    api.loop_step(ud, Td, spec.L, g["dtau"], K.IMEX, g["steps"])
+    J = api.loop_cost(ud, Td, spec.L).item()
+    assert J < g["J_tol"], J
+    assert abs(J - g["J_final"]) <= 1e-3 * g["J_final"]
+    assert abs(Td.item() - g["T_final"]) <= 1e-8
+    u = ud.cpu().numpy()[0]
+    worst = max(abs(abs(u[k % spec.Ns, j]) - a) for j, k, a in g["abs_uhat_final_band"])
+    assert worst <= 1e-8, worst
+    assert g["end_state"] == "equilibrium"
