@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+CUS = 256
 PASS_NAMES = {1: "B (rows: u u_x)", 2: "C (columns: residual, J, dJ/dT)", 3: "D (rows: u r_x, period)",
               4: "E (columns: G and update, next A)"}
 
@@ -68,6 +70,18 @@ def pass_bytes(shapes, p):
     return 16 * tot
 
 
+def step_flops(Nx, Ns):
+    """Algorithmic FP64 flops of one step of one loop (5 n log2 n per complex n-point transform):
+    four transforms per band column (C: forward and inverse; E: forward and the next step's
+    inverse), three per row over passes B and D (each pass: two inverse and one forward per
+    pair of rows), about 55 per band value for the spectral assembly and update, and the
+    physical-space products."""
+    C = (Nx - 1) // 3 + 1
+    S = C * (2 * ((Ns - 1) // 3) + 1)
+    lg = lambda n: n.bit_length() - 1
+    return 20 * C * Ns * lg(Ns) + 15 * Ns * Nx * lg(Nx) + 55 * S + 4 * Nx * Ns
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch from the committed counter summary, if it was taken on this source."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
@@ -106,6 +120,8 @@ def main():
     api.init()
     dev = "cuda:0"
     stream = torch.cuda.current_stream()
+    if nl == 1 and api.step_form(specs[0].Nx, specs[0].Ns, 1) == "resident":
+        return bench_resident(args, cfg, specs[0], steps, dtau, scheme)
     batch = api.Batch([(s.L, s.Nx, s.Ns) for s in specs])
     pool0 = batch.pack([torch.from_numpy(s.uhat) for s in specs])
     T0 = torch.tensor([s.T for s in specs], dtype=torch.float64, device=dev)
@@ -226,6 +242,65 @@ def main():
         "autotune": {"pass_us": tuning["pass_us"], "step_us": tuning["step_us"]},
         "batched_vs_plain": (value / plain["value"]) if plain else None,
         "J_first_last": [float(J[0].mean()), float(J[-1].mean())],
+    }
+    print(json.dumps(out))
+
+
+def bench_resident(args, cfg, spec, steps, dtau, scheme):
+    """One loop through loop_step, which takes it in the LDS-resident form: one block, every
+    step in a single launch. That kernel is bound by FP64 arithmetic and LDS latency on the one
+    CU it occupies, so its roofline is FP64 flops against the vector peak (and per CU used)."""
+    import numpy as np
+    import torch
+
+    from paper_2007_06427_amd import api
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream()
+    u0 = torch.from_numpy(spec.uhat[None]).to(dev)
+    T0 = torch.tensor([spec.T], dtype=torch.float64, device=dev)
+    ws = api.Workspace(api.workspace_bytes(spec.Nx, spec.Ns, 1))
+    u, T = u0.clone(), T0.clone()
+    api.loop_step(u, T, spec.L, dtau, scheme, args.warmup, ws=ws)
+    torch.cuda.synchronize()
+    assert ws.status() == 0
+    u, T = u0.clone(), T0.clone()
+    Jh = torch.zeros(steps, 1, dtype=torch.float64, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    api.loop_step(u, T, spec.L, dtau, scheme, steps, J_hist=Jh, ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert ws.status() == 0, "device flagged a non-finite state"
+    J = Jh.cpu().numpy()[:, 0]
+    assert np.all(np.isfinite(J))
+    pts = spec.Nx * spec.Ns
+    gpu_s = e0.elapsed_time(e1) * 1e-3
+    fl = step_flops(spec.Nx, spec.Ns)
+    achieved = fl * steps / gpu_s / 1e12
+    # a plain device copy of known size (counter calibration, as in the batched workloads)
+    src = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
+    torch.empty_like(src).copy_(src)
+    torch.cuda.synchronize()
+    cpu = None if args.no_cpu else cpu_baseline([spec], dtau, scheme)
+    out = {
+        "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
+        "value": pts * steps / wall, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "loops": 1, "shapes": [[spec.Nx, spec.Ns]], "scheme": cfg["scheme"],
+                   "dtau": dtau, "form": "resident (one block, all steps in one launch)",
+                   "parallelism": "none (1 GPU)"},
+        "gpu_ms_per_step": gpu_s / steps * 1e3,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP64_PEAK_TFLOPS, 6), "traffic": None,
+                     "kernel": f"k_resident<{spec.Nx}, {spec.Ns}>", "flops_per_step": fl,
+                     "avg_launch_us": round(gpu_s * 1e6, 1), "cus_used": 1,
+                     "frac_of_cus_used": round(achieved / (FP64_PEAK_TFLOPS / CUS), 4)},
+        "cpu_baseline": cpu,
+        "J_first_last": [float(J[0]), float(J[-1])],
     }
     print(json.dumps(out))
 

@@ -108,6 +108,25 @@ int loop_cost_grad(double L, int Nx, int Ns, int nloops, const double* T, const 
 int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau,
               int scheme, int nsteps, double* J_hist, void* ws, size_t ws_bytes, void* stream);
 
+/* loop_step runs in one of two forms, with the same results:
+ *   resident: one block per loop holds the loop's band state and intermediates in LDS and
+ *     takes every step in a single launch; HBM traffic is the state's load and store. It
+ *     exists where the loop's working set fits one CU's LDS (loop_resident_supported);
+ *   per-pass: five kernels per step over all loops, intermediates in the work space (HBM).
+ * A step of the resident form equals the per-pass form of loop_batch_step (and of loop_step
+ * with nloops = 1) bit for bit; with nloops > 1 and Ns below the row-tile height the two pair
+ * rows of different loops differently in the row transforms and agree to rounding.
+ * loop_set_resident(mode) sets the choice for later calls in this process: 0 per-pass always,
+ * 1 (default) resident where it was measured faster (at most one loop per CU, and for shapes
+ * whose passes take two rounds per block, at least 16 loops), 2 resident wherever it exists.
+ * It returns the previous mode, or LOOP_EINVAL for other values.
+ * loop_resident_supported returns 1 when the resident form exists for an Nx x Ns loop on the
+ * current device, else 0. loop_step_form returns the form loop_step takes for nloops loops of
+ * Nx x Ns under the current mode: 1 resident, 0 per-pass (LOOP_EINVAL for a bad shape). */
+int loop_set_resident(int mode);
+int loop_resident_supported(int Nx, int Ns);
+int loop_step_form(int Nx, int Ns, int nloops);
+
 /* The update half of loop_step, for a G_1 computed elsewhere (e.g. by autograd):
  * uhat <- canonical(uhat) + dtau * sigma * Ghat (band), T <- T - dtau * dJdT[l]. */
 int loop_update(double L, int Nx, int Ns, int nloops, double* T, double* uhat,

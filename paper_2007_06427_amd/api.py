@@ -154,6 +154,32 @@ def loop_step(uhat: torch.Tensor, T: torch.Tensor, L: float, dtau: float, scheme
     return uhat, T
 
 
+RESIDENT_NEVER, RESIDENT_AUTO, RESIDENT_ALWAYS = 0, 1, 2
+
+
+def set_resident(mode: int) -> int:
+    """Choose the form of loop_step for later calls: RESIDENT_NEVER (per-pass kernels),
+    RESIDENT_AUTO (the default: resident where measured faster) or RESIDENT_ALWAYS (resident
+    wherever the loop fits in LDS). Returns the previous mode."""
+    prev = _lib.lib().loop_set_resident(int(mode))
+    if prev < 0:
+        check(prev, "loop_set_resident")
+    return prev
+
+
+def step_form(Nx: int, Ns: int, nloops: int = 1) -> str:
+    """"resident" or "per-pass": the form loop_step takes for these loops under the current mode."""
+    f = _lib.lib().loop_step_form(int(Nx), int(Ns), int(nloops))
+    if f < 0:
+        check(f, "loop_step_form")
+    return "resident" if f == 1 else "per-pass"
+
+
+def resident_supported(Nx: int, Ns: int) -> bool:
+    """Whether loop_step takes an Nx x Ns loop in the LDS-resident form on this device."""
+    return bool(_lib.lib().loop_resident_supported(int(Nx), int(Ns)))
+
+
 def loop_update(uhat: torch.Tensor, T: torch.Tensor, L: float, Ghat: torch.Tensor, dJdT: torch.Tensor,
                 dtau: float, scheme: int = EXPLICIT):
     nl, Nx, Ns = shape_of(uhat)

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -14,6 +15,7 @@
 
 #include "looporbit.h"
 #include "passes.hpp"
+#include "resident.hpp"
 
 using namespace lo;
 
@@ -480,6 +482,97 @@ void launch_rag(int v, dim3 grid, size_t lds, hipStream_t hs, const BatchArgs& a
     }
 }
 
+// LDS-resident step (see resident.hpp): block l runs all nsteps of loop l with its state and
+// intermediates in LDS. The rfft-layout spectrum is read at the start and written back at
+// the end (the same arithmetic as k_to_band and k_from_band), T[l] likewise.
+// The twiddle table's address as seen by one pass: an opaque copy, so that the compiler does
+// not hoist every pass's twiddle cache out of the step loop and keep them all live at once.
+__device__ __forceinline__ const cd* per_pass(const cd* tw) {
+    asm volatile("" : "+s"(tw));
+    return tw;
+}
+
+// LDS-resident step (see resident.hpp): block l runs all nsteps of loop l with its state and
+// intermediates in LDS. The rfft-layout spectrum is read at the start and written back at
+// the end (the same arithmetic as k_to_band and k_from_band), T[l] likewise.
+template <int M, int N>
+__global__ __launch_bounds__(kBlock) void k_resident(Shape sh, const cd* uin, cd* uout, double* T, double dtau,
+                                                     int scheme, int nsteps, double* J_hist, int* status,
+                                                     const cd* __restrict__ tw) {
+    using R = ResG<M, N>;
+    extern __shared__ cd lds[];
+    cd* U = lds;
+    cd* A = U + R::S;
+    cd* X = A + R::W;
+    cd* EX = X + R::W;
+    double* part = reinterpret_cast<double*>(EX + R::EX);
+    double* sc = part + 2 * R::C;  // T, T_old, J, dJ/dT
+    double* red = sc + 4;          // 2 kBlock / 64 doubles
+    const int l = blockIdx.x;
+    Shape s1 = sh;
+    s1.nloops = 1;
+    Work w;
+    w.A = A;
+    w.BD = X;
+    w.Cb = X;
+    w.U = U;
+    w.G = U;
+    w.partial = part;
+    w.J = sc + 2;
+    w.dJdT = sc + 3;
+    w.Told = sc + 1;
+    w.status = status;
+    const cd* u = uin + (size_t)l * N * sh.H;
+    for (int i = threadIdx.x; i < R::S; i += kBlock) {
+        const int j = i / R::NB, kk = i % R::NB;
+        const int e = (kk <= R::Ks) ? kk : kk + N - R::NB;
+        cd v = u[(size_t)e * sh.H + j];
+        if (j == 0) {
+            const cd pr = u[(size_t)((N - e) & (N - 1)) * sh.H];
+            v = cd{0.5 * (v.x + pr.x), 0.5 * (v.y - pr.y)};
+        }
+        U[i] = v;
+    }
+    if (threadIdx.x == 0) sc[0] = T[l];
+    __syncthreads();
+    if (nsteps > 0) {
+#pragma unroll 1
+        for (int b = 0; b < R::COL_ROUNDS; ++b) col_pass_A<N>(s1, b, w, EX, per_pass(tw));
+        __syncthreads();
+    }
+    for (int st = 0; st < nsteps; ++st) {
+#pragma unroll 1
+        for (int tile = 0; tile < R::ROW_ROUNDS; ++tile) res_row_B<M>(s1, tile, A, X, EX, per_pass(tw));
+        __syncthreads();
+#pragma unroll 1
+        for (int b = 0; b < R::COL_ROUNDS; ++b)
+            col_pass_C<N>(s1, b, sc, w, MODE_STEP, dtau, scheme, EX, red, per_pass(tw));
+        __syncthreads();
+        // J, dJ/dT and T' from pass C's partials; pass D reads neither T nor the partials
+        if (threadIdx.x < 64)
+            finalize_loop(s1, 0, w, sc, MODE_STEP, dtau, J_hist ? J_hist + (size_t)st * gridDim.x + l : nullptr,
+                          nullptr, nullptr);
+#pragma unroll 1
+        for (int tile = 0; tile < R::ROW_ROUNDS; ++tile) res_row_D<M>(s1, tile, A, X, EX, per_pass(tw));
+        __syncthreads();
+#pragma unroll 1
+        for (int b = 0; b < R::COL_ROUNDS; ++b)
+            col_pass_E<N>(s1, b, w, MODE_STEP, dtau, scheme, st + 1 < nsteps, EX, per_pass(tw));
+        __syncthreads();
+    }
+    cd* o = uout + (size_t)l * N * sh.H;
+    for (int i = threadIdx.x; i < N * sh.H; i += kBlock) {
+        const int e = i / sh.H, j = i % sh.H;
+        cd v{0.0, 0.0};
+        if (j < R::C) {
+            const int kk = band_row(e, N, R::Ks);
+            if (kk >= 0) v = U[j * R::NB + kk];
+        }
+        o[i] = v;
+    }
+    if (threadIdx.x == 0) T[l] = sc[0];
+}
+
 // rfft-layout pool -> per-loop band state (blockIdx.z = loop); see k_to_band.
 __global__ __launch_bounds__(256) void k_to_band_batch(const BatchLoop* loops, const cd* __restrict__ pool,
                                                        char* ws) {
@@ -687,6 +780,17 @@ int prepare(double L, int Nx, int Ns, int nloops, void* ws, size_t ws_bytes, Sha
         default: return LOOP_ENOTSUP;                        \
     }
 
+// Calls f(std::integral_constant<int, S>) for the power of two S == n in [LO, HI].
+template <int LO, int HI, class F>
+void host_size_switch(int n, F&& f) {
+    if constexpr (LO <= HI) {
+        if (n == LO)
+            f(std::integral_constant<int, LO>{});
+        else
+            host_size_switch<2 * LO, HI>(n, static_cast<F&&>(f));
+    }
+}
+
 unsigned col_blocks(const Shape& s) {
     const int F = 8 * kBlock / s.N;  // columns per block
     return (unsigned)(((size_t)s.nloops * s.C + F - 1) / F);
@@ -731,6 +835,82 @@ void launch_from_band(const Shape& s, const cd* src, cd* out, hipStream_t st) {
     hipLaunchKernelGGL(k_from_band, grid, dim3(256), 0, st, s, src, out);
 }
 
+// ---------------------------------------------------------------------------- resident form
+int last_error() { return hipGetLastError() == hipSuccess ? LOOP_OK : LOOP_EHIP; }
+
+// loop_set_resident: 0 never, 1 where measured faster (default), 2 wherever it fits
+std::atomic<int> g_resident{1};
+
+int max_lds_per_block() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    return v;
+}
+
+// LDS bytes of the resident step for this shape, or 0 where it has no kernel.
+size_t resident_bytes(int Nx, int Ns) {
+    size_t b = 0;
+    host_size_switch<8, 128>(Nx, [&](auto m) {
+        host_size_switch<8, 512>(Ns, [&](auto n) {
+            using R = ResG<decltype(m)::value, decltype(n)::value>;
+            if constexpr (R::FITS) b = R::BYTES;
+        });
+    });
+    return b;
+}
+
+bool resident_usable(int Nx, int Ns) {
+    const size_t b = resident_bytes(Nx, Ns);
+    return b > 0 && b <= (size_t)max_lds_per_block();
+}
+
+// Whether one resident block covers a pass of this shape in a single round of transforms.
+bool resident_one_round(int Nx, int Ns) {
+    bool one = false;
+    host_size_switch<8, 128>(Nx, [&](auto m) {
+        host_size_switch<8, 512>(Ns, [&](auto n) {
+            using R = ResG<decltype(m)::value, decltype(n)::value>;
+            if constexpr (R::FITS) one = R::COL_ROUNDS == 1 && R::ROW_ROUNDS == 1;
+        });
+    });
+    return one;
+}
+
+// The automatic choice, from measurements on MI355X (one 4-wavefront block per loop is
+// latency-bound; the per-pass form spreads a pass over more CUs but pays HBM round trips):
+// resident wins while every loop gets a CU of its own (nloops up to the CU count), except a
+// lone loop or a few loops whose passes need two rounds per block (32 x 256, 64 x 128).
+bool resident_preferred(int Nx, int Ns, int nloops) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return false;
+    if (nloops > cus) return false;
+    return resident_one_round(Nx, Ns) || nloops >= 16;
+}
+
+int launch_resident(const Shape& s, cd* u, double* T, double dtau, int scheme, int nsteps, double* J_hist,
+                    int* status, const cd* tw, hipStream_t hs) {
+    int st = LOOP_ENOTSUP;
+    host_size_switch<8, 128>(s.M, [&](auto m) {
+        host_size_switch<8, 512>(s.N, [&](auto n) {
+            constexpr int M_ = decltype(m)::value, N_ = decltype(n)::value;
+            using R = ResG<M_, N_>;
+            if constexpr (R::FITS) {
+                auto k = k_resident<M_, N_>;
+                hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)R::BYTES);
+                hipLaunchKernelGGL(k, dim3(s.nloops), dim3(kBlock), R::BYTES, hs, s, u, u, T, dtau, scheme, nsteps,
+                                   J_hist, status, tw);
+                st = last_error();
+            }
+        });
+    });
+    return st;
+}
+
 // ---------------------------------------------------------------------------- batch plans
 struct BatchPlan {
     int device = -1;
@@ -761,15 +941,6 @@ size_t pass_lds_bytes(const Shape& s) {
     const int rows = 4096 / s.M, cmax = (s.M - 1) / 3 + 1;
     const size_t row = std::max<size_t>(2 * (size_t)cmax * (rows + 1), 2304);
     return std::max(col, row) * sizeof(cd);
-}
-template <int LO, int HI, class F>
-void host_size_switch(int n, F&& f) {
-    if constexpr (LO <= HI) {
-        if (n == LO)
-            f(std::integral_constant<int, LO>{});
-        else
-            host_size_switch<2 * LO, HI>(n, static_cast<F&&>(f));
-    }
 }
 // Dynamic LDS of one pass of the launch-per-pass form for a loop of this shape.
 size_t rag_lds_bytes(const Shape& s, int pass) {
@@ -819,7 +990,6 @@ unsigned elem_blocks(size_t n) {
     return (unsigned)(b ? b : 1);
 }
 
-int last_error() { return hipGetLastError() == hipSuccess ? LOOP_OK : LOOP_EHIP; }
 
 }  // namespace
 
@@ -972,6 +1142,8 @@ int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, dou
     if (st) return st;
     hipStream_t hs = (hipStream_t)stream;
     cd* u = reinterpret_cast<cd*>(uhat);
+    if (loop_step_form(Nx, Ns, nloops) == 1)
+        return launch_resident(s, u, T, dtau, scheme, nsteps, J_hist, w.status, tw, hs);
     launch_to_band(s, u, w.U, hs);
     if (nsteps > 0 && (st = launch_A(s, w, tw, hs))) return st;
     for (int i = 0; i < nsteps; ++i) {
@@ -983,6 +1155,22 @@ int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, dou
     }
     launch_from_band(s, w.U, u, hs);
     return last_error();
+}
+
+int loop_set_resident(int mode) {
+    if (mode < 0 || mode > 2) return LOOP_EINVAL;
+    return g_resident.exchange(mode);
+}
+
+int loop_resident_supported(int Nx, int Ns) {
+    if (check_shape(22.0, Nx, Ns, 1)) return 0;
+    return resident_usable(Nx, Ns) ? 1 : 0;
+}
+
+int loop_step_form(int Nx, int Ns, int nloops) {
+    if (check_shape(22.0, Nx, Ns, nloops)) return LOOP_EINVAL;
+    const int mode = g_resident.load();
+    return (mode != 0 && resident_usable(Nx, Ns) && (mode == 2 || resident_preferred(Nx, Ns, nloops))) ? 1 : 0;
 }
 
 int loop_update(double L, int Nx, int Ns, int nloops, double* T, double* uhat, const double* Ghat,

@@ -244,7 +244,8 @@ def test_trajectory_plain64x128_imex(api):
     assert np.all(np.diff(Jh) <= 0)
 
 
-def test_reaches_the_oracle_converged_state(api):
+@pytest.mark.parametrize("form", [0, 2])
+def test_reaches_the_oracle_converged_state(api, form):
     """Convergence parity: from the 32 x 32 workload's seed, IMEX at dtau = 0.05, the oracle
     needed the stored number of steps to bring J below 1e-10 (it ends on an equilibrium).
     The GPU run of the same steps must end with J < 1e-10, T within 1e-8 of the oracle's,
@@ -254,7 +255,12 @@ def test_reaches_the_oracle_converged_state(api):
     spec = loopgen.config_loops(1)[0]
     assert (spec.Nx, spec.Ns, spec.L, spec.T) == (g["Nx"], g["Ns"], g["L"], g["T0"])
     ud, Td = to_dev(spec.uhat[None], np.array([spec.T]))
-    api.loop_step(ud, Td, spec.L, g["dtau"], K.IMEX, g["steps"])
+    prev = api.set_resident(form)  # 0: per-pass kernels, 2: the LDS-resident kernel
+    try:
+        assert api.step_form(spec.Nx, spec.Ns) == ("resident" if form == 2 else "per-pass")
+        api.loop_step(ud, Td, spec.L, g["dtau"], K.IMEX, g["steps"])
+    finally:
+        api.set_resident(prev)
     J = api.loop_cost(ud, Td, spec.L).item()
     assert J < g["J_tol"], J
     assert abs(J - g["J_final"]) <= 1e-3 * g["J_final"]
