@@ -9,6 +9,8 @@ are seeded synthetic loops, already resident in HBM when the timed region starts
 Workloads:
   batched-ragged-256  (default) 256 loops, Nx in {32, 64}, Ns in {64..512}, L in {22, 39}, IMEX
   batched-256x1024    64 loops of 256 x 1024, L = 100, IMEX
+  autograd-256x1024   the same 64 loops, G from the autograd path (LoopCost forward and its
+                      adjoint backward) and the update by loop_update
   plain-64x128        one 64 x 128 loop, L = 22, IMEX
   plain-32x32         one 32 x 32 loop, L = 22, explicit Euler
 
@@ -35,6 +37,7 @@ PASS_NAMES = {1: "B (rows: u u_x)", 2: "C (columns: residual, J, dJ/dT)", 3: "D 
 WORKLOADS = {
     "batched-ragged-256": 4,
     "batched-256x1024": 5,
+    "autograd-256x1024": 5,
     "plain-64x128": 2,
     "plain-32x32": 1,
 }
@@ -122,6 +125,8 @@ def main():
     stream = torch.cuda.current_stream()
     if nl == 1 and api.step_form(specs[0].Nx, specs[0].Ns, 1) == "resident":
         return bench_resident(args, cfg, specs[0], steps, dtau, scheme)
+    if args.workload.startswith("autograd"):
+        return bench_autograd(args, cfg, specs, steps, dtau, scheme)
     batch = api.Batch([(s.L, s.Nx, s.Ns) for s in specs])
     pool0 = batch.pack([torch.from_numpy(s.uhat) for s in specs])
     T0 = torch.tensor([s.T for s in specs], dtype=torch.float64, device=dev)
@@ -301,6 +306,83 @@ def bench_resident(args, cfg, spec, steps, dtau, scheme):
                      "frac_of_cus_used": round(achieved / (FP64_PEAK_TFLOPS / CUS), 4)},
         "cpu_baseline": cpu,
         "J_first_last": [float(J[0]), float(J[-1])],
+    }
+    print(json.dumps(out))
+
+
+def autograd_bytes(Nx, Ns):
+    """Algorithmic HBM bytes of one autograd-path step of one loop (16 B per complex value;
+    R = Ns (Nx/2 + 1) values of the rfft-layout spectrum, S band values, W values of one
+    intermediate). Forward loop_cost: R + 3S + 4W (band conversion, passes A, B, C). Backward
+    loop_cost_grad: 2R + 7S + 9W (conversion, passes A-E, gradient out). G = -grad / (w_j L):
+    2R. loop_update: 3R."""
+    C = (Nx - 1) // 3 + 1
+    S = C * (2 * ((Ns - 1) // 3) + 1)
+    W = C * Ns
+    R = Ns * (Nx // 2 + 1)
+    return 16 * (8 * R + 10 * S + 13 * W)
+
+
+def bench_autograd(args, cfg, specs, steps, dtau, scheme):
+    """The large batched workload through the differentiable form: per step, J = LoopCost(u, T)
+    forward, J.sum().backward() (the hand-written adjoint kernel), G_1 = -grad / (w_j L) and
+    loop_update. The roofline is the whole step's algorithmic bytes over its time."""
+    import numpy as np
+    import torch
+
+    from paper_2007_06427_amd import api, autograd
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream()
+    L = specs[0].L
+    Nx, Ns = specs[0].Nx, specs[0].Ns
+    assert all((s.L, s.Nx, s.Ns) == (L, Nx, Ns) for s in specs)
+    u0 = torch.from_numpy(np.stack([s.uhat for s in specs])).to(dev)
+    T0 = torch.tensor([s.T for s in specs], dtype=torch.float64, device=dev)
+    w = torch.full((Nx // 2 + 1,), 2.0, dtype=torch.float64, device=dev)
+    w[0] = 1.0
+    winv = (-1.0 / (w * L)).to(torch.complex128)
+
+    def run(u, T, k):
+        for _ in range(k):
+            ua = u.detach().requires_grad_(True)
+            Ta = T.detach().requires_grad_(True)
+            autograd.LoopCost.apply(ua, Ta, L).sum().backward()
+            G = ua.grad.mul_(winv)
+            api.loop_update(u, T, L, G, Ta.grad, dtau, scheme)
+
+    u, T = u0.clone(), T0.clone()
+    run(u, T, args.warmup)
+    torch.cuda.synchronize()
+    u, T = u0.clone(), T0.clone()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    run(u, T, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    J = api.loop_cost(u, T, L).cpu().numpy()
+    assert np.all(np.isfinite(J)) and torch.all(T > 0)
+    pts = Nx * Ns * len(specs)
+    by = autograd_bytes(Nx, Ns) * len(specs)
+    gpu_s = e0.elapsed_time(e1) * 1e-3
+    achieved = by * steps / gpu_s / 1e9
+    out = {
+        "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
+        "value": pts * steps / wall, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "loops": len(specs), "shapes": [[Nx, Ns]], "scheme": cfg["scheme"],
+                   "dtau": dtau, "form": "autograd G (LoopCost backward) + loop_update",
+                   "parallelism": "none (1 GPU)"},
+        "gpu_ms_per_step": gpu_s / steps * 1e3,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "whole autograd step (forward, adjoint backward, G, update)",
+                     "bytes_per_step": by},
+        "cpu_baseline": None,
+        "J_mean_end": float(J.mean()),
     }
     print(json.dumps(out))
 
