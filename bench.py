@@ -161,7 +161,8 @@ def main():
     assert np.all(np.isfinite(J))
     value = pts_step * steps / wall
 
-    # ---- per-kernel timing, pass by pass, with events on the launch stream. Every pass is a
+    # ---- per-kernel timing, pass by pass (each pass over every loop, alone on the stream, as
+    # the per-pass schedule runs it), with events on the launch stream. Every pass is a
     # function of the work space alone, so pass p is launched R times back to back between one
     # event pair; the launches take a negligible step (a kernel's work does not depend on it),
     # so that pass D's repeated period updates leave T where it is. A backlog of queued whole
@@ -195,7 +196,10 @@ def main():
                 "avg_launch_us": round(avg_us[dom], 2),
                 "passes_us": {kernel_of(p): round(v, 2) for p, v in avg_us.items()},
                 "passes_sum_vs_step": round(passes_sum_us / (step_s * 1e6), 3),
-                "step_bytes": step_bytes}
+                "step_bytes": step_bytes,
+                # the whole step, every pass, as the timed region ran it (its kernels may overlap)
+                "step_achieved": round(step_bytes / (e0.elapsed_time(e1) * 1e-3 / steps) / 1e9, 1),
+                "step_frac": round(step_bytes / (e0.elapsed_time(e1) * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS, 4)}
     if tuning["schedule"] == "persistent":
         # the timed region ran one persistent launch over all steps: that kernel is the one
         gpu_s = e0.elapsed_time(e1) * 1e-3

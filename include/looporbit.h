@@ -146,13 +146,21 @@ int loop_update(double L, int Nx, int Ns, int nloops, double* T, double* uhat,
  * loop_batch_set_schedule), and the conversion back. Its work space
  * (loop_batch_info bytes) must be prepared once by loop_batch_workspace_init. After a
  * LOOP_EHANG status, prepare it again before reuse. */
-typedef enum { LOOP_BATCH_PER_PASS = 0, LOOP_BATCH_PERSISTENT = 1 } loop_batch_schedule;
+typedef enum { LOOP_BATCH_PER_PASS = 0, LOOP_BATCH_PERSISTENT = 1, LOOP_BATCH_STREAMS = 2 } loop_batch_schedule;
 int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns, void** plan);
 /* Choose how loop_batch_step runs the steps (results are identical bit for bit):
  *   LOOP_BATCH_PER_PASS (default): one kernel per pass over every loop's tiles, four per step;
  *   LOOP_BATCH_PERSISTENT: one launch for all steps, blocks pulling (pass, loop, tile) items
- *   in dependency order (see the scheduler notes in the source). */
+ *   in dependency order (see the scheduler notes in the source);
+ *   LOOP_BATCH_STREAMS: the loops split into K groups of about equal work (K from
+ *   loop_batch_set_streams, 2 to 4, default 2), group 0 on `stream` and the others on streams
+ *   the plan owns (default priority), each started one pass after the previous group, so that
+ *   different passes of different groups run side by side as separate kernels. The plan's
+ *   streams are forked from and joined back to `stream` with events, so the call stays
+ *   ordered on `stream` and can be captured in a graph from it. Calls with one plan must not
+ *   overlap (the plan's streams and events are shared). */
 int loop_batch_set_schedule(void* plan, int schedule);
+int loop_batch_set_streams(void* plan, int nstreams);
 int loop_batch_destroy(void* plan);
 int loop_batch_info(const void* plan, size_t* ws_bytes, size_t* pool_elems, long long* uhat_offsets);
 int loop_batch_workspace_init(const void* plan, void* ws, size_t ws_bytes, void* stream);
@@ -174,13 +182,18 @@ int loop_batch_pass(const void* plan, int pass, int step, int nsteps, double* T,
                     double* J_hist, void* ws, size_t ws_bytes, void* stream);
 int loop_batch_store(const void* plan, double* uhat_pool, void* ws, size_t ws_bytes, void* stream);
 
-/* Kernel variants and the autotuner (per-pass schedule). Each pass has LOOP_BATCH_VARIANTS
- * kernel variants that run the same arithmetic (results are identical bit for bit) and
- * differ in the range of transform sizes compiled in, hence register use and wavefronts
- * per SIMD, and, for the row passes B and D, in how tiles of rows reach LDS:
+/* Kernel variants and the autotuner (per-pass schedule). Each pass has up to
+ * LOOP_BATCH_VARIANTS kernel variants. They differ in the range of transform sizes compiled
+ * in (hence register use and wavefronts per SIMD) and, for the row passes B and D, in how
+ * tiles of rows reach LDS and in the FFT tile shape:
  *   row passes:    0 sizes 8..512 staged through registers; 1 sizes 8..64 staged;
  *                  2 sizes 8..64 copied by the load unit straight into LDS;
+ *                  3 sizes 8..64 staged, 4 points per thread (8 elsewhere): twice the
+ *                    threads per row transform, half-height tiles;
  *   column passes: 0 sizes 8..1024; 1 sizes 8..64; 2 sizes 8..512.
+ * Variants 0-2 of a pass run the same arithmetic, so they agree bit for bit. Row variant 3
+ * pairs rows and factors the transforms differently and agrees to rounding (it meets the
+ * same 1e-12 per-step bound against the definitions).
  * A variant is usable for a plan when its size range covers every loop's Nx (row passes)
  * or Ns (column passes). A new plan takes the narrowest staged variant for every pass, or
  * the configuration an earlier loop_batch_autotune chose for a plan with the same multiset
@@ -188,23 +201,25 @@ int loop_batch_store(const void* plan, double* uhat_pool, void* ws, size_t ws_by
  *
  * loop_batch_set_variant: pass 0..4, variant 0..LOOP_BATCH_VARIANTS-1; LOOP_EINVAL when the
  * variant does not cover the plan's sizes.
- * loop_batch_get_config: any output pointer may be NULL; variants receives 5 ints.
+ * loop_batch_get_config: any output pointer may be NULL; variants receives 5 ints, nstreams
+ * the stream count of the multi-stream schedule.
  *
  * loop_batch_autotune times, on the caller's state (T[nloops], uhat_pool as for
  * loop_batch_step; neither is modified), every usable variant of every pass over `reps`
  * back-to-back launches (best of three trials, hipEvent timing on `stream`), keeps the
- * fastest per pass, then times `reps` whole steps of each schedule and keeps the faster.
- * The work of every kernel is independent of dtau and scheme, so the timing runs use a
- * step of 1e-30 (IMEX), which leaves the state unchanged to the last bit in practice and
- * keeps every repetition finite. It allocates temporary device copies of T and the pool,
- * synchronises `stream`, and overwrites the work space's intermediates (the work space
- * stays prepared). reps in [1, 1000]. report, if not NULL, receives 5 * LOOP_BATCH_VARIANTS + 2 doubles: the mean
- * microseconds per launch of (pass, variant) at index pass * LOOP_BATCH_VARIANTS + variant
- * (-1 for variants not usable), then microseconds per step of the per-pass and the
- * persistent schedule. Returns a device status raised while timing, else LOOP_OK. */
-#define LOOP_BATCH_VARIANTS 3
+ * fastest per pass, then times `reps` whole steps of each schedule (the multi-stream one with
+ * 2, 3 and 4 streams) and keeps the fastest. The work of every kernel is independent of dtau
+ * and scheme, so the timing runs use a step of 1e-30 (IMEX), which leaves the state unchanged
+ * to the last bit in practice and keeps every repetition finite. It allocates temporary
+ * device copies of T and the pool, synchronises `stream`, and overwrites the work space's
+ * intermediates (the work space stays prepared). reps in [1, 1000]. report, if not NULL,
+ * receives 5 * LOOP_BATCH_VARIANTS + 5 doubles: the mean microseconds per launch of (pass,
+ * variant) at index pass * LOOP_BATCH_VARIANTS + variant (-1 for variants not usable), then
+ * microseconds per step of the per-pass, the persistent, and the multi-stream schedule with
+ * 2, 3 and 4 streams. Returns a device status raised while timing, else LOOP_OK. */
+#define LOOP_BATCH_VARIANTS 4
 int loop_batch_set_variant(void* plan, int pass, int variant);
-int loop_batch_get_config(const void* plan, int* schedule, int* variants);
+int loop_batch_get_config(const void* plan, int* schedule, int* variants, int* nstreams);
 int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, int reps, double* report, void* ws,
                         size_t ws_bytes, void* stream);
 

@@ -25,7 +25,8 @@ IMEX = 1
 EXPORTS = [
     "loop_init", "loop_shutdown", "loop_workspace_bytes", "loop_workspace_init", "loop_residual",
     "loop_cost", "loop_adjoint_grad", "loop_cost_grad", "loop_step", "loop_set_resident",
-    "loop_resident_supported", "loop_step_form", "loop_update", "loop_batch_create", "loop_batch_set_schedule", "loop_batch_destroy",
+    "loop_resident_supported", "loop_step_form", "loop_update", "loop_batch_create", "loop_batch_set_schedule", "loop_batch_set_streams",
+    "loop_batch_destroy",
     "loop_batch_info", "loop_batch_workspace_init", "loop_batch_step", "loop_batch_load", "loop_batch_pass",
     "loop_batch_store", "loop_batch_set_variant", "loop_batch_get_config", "loop_batch_autotune",
     "loop_status_sync", "loop_status_string",
@@ -62,6 +63,7 @@ _SIGS = {
     "loop_resident_supported": ([_i, _i], _i),
     "loop_step_form": ([_i, _i, _i], _i),
     "loop_batch_set_schedule": ([_p, _i], _i),
+    "loop_batch_set_streams": ([_p, _i], _i),
     "loop_batch_destroy": ([_p], _i),
     "loop_batch_info": ([_p, ctypes.POINTER(_sz), ctypes.POINTER(_sz), ctypes.POINTER(ctypes.c_longlong)], _i),
     "loop_batch_workspace_init": ([_p, _p, _sz, _p], _i),
@@ -70,7 +72,7 @@ _SIGS = {
     "loop_batch_pass": ([_p, _i, _i, _i, _p, _d, _i, _p, _p, _sz, _p], _i),
     "loop_batch_store": ([_p, _p, _p, _sz, _p], _i),
     "loop_batch_set_variant": ([_p, _i, _i], _i),
-    "loop_batch_get_config": ([_p, ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
+    "loop_batch_get_config": ([_p, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
     "loop_batch_autotune": ([_p, _p, _p, _i, ctypes.POINTER(_d), _p, _sz, _p], _i),
     "loop_status_sync": ([_p, _p], _i),
     "loop_status_string": ([_i], ctypes.c_char_p),

@@ -190,7 +190,7 @@ def loop_update(uhat: torch.Tensor, T: torch.Tensor, L: float, Ghat: torch.Tenso
 
 
 class Batch:
-    """Loops of uneven (L, Nx, Ns) advanced together by the persistent batched kernel.
+    """Loops of uneven (L, Nx, Ns) advanced together by the batched kernels.
 
     The spectra live back to back in one complex128 pool (rfft layout per loop, in the order
     given); `offsets[l]` is loop l's first element. The plan's device tables and the work
@@ -219,12 +219,16 @@ class Batch:
 
     PER_PASS = 0
     PERSISTENT = 1
+    STREAMS = 2
 
-    def set_schedule(self, schedule: int):
-        """PER_PASS (four launches per step) or PERSISTENT (one launch for all steps)."""
+    def set_schedule(self, schedule: int, nstreams: int = None):
+        """PER_PASS (four launches per step), PERSISTENT (one launch for all steps) or STREAMS
+        (the loops in nstreams groups, 2 to 4, on as many streams, one pass apart)."""
         check(_lib.lib().loop_batch_set_schedule(self._plan, int(schedule)), "loop_batch_set_schedule")
+        if nstreams is not None:
+            check(_lib.lib().loop_batch_set_streams(self._plan, int(nstreams)), "loop_batch_set_streams")
 
-    VARIANTS = 3
+    VARIANTS = 4
     PASS_NAMES = ("A", "B", "C", "D", "E")
 
     def set_variant(self, pass_id: int, variant: int):
@@ -233,18 +237,19 @@ class Batch:
 
     def config(self) -> dict:
         """The schedule and the kernel variant of each pass currently in use."""
-        sc = ctypes.c_int(0)
+        sc, ns = ctypes.c_int(0), ctypes.c_int(0)
         v = (ctypes.c_int * 5)()
-        check(_lib.lib().loop_batch_get_config(self._plan, ctypes.byref(sc), v), "loop_batch_get_config")
-        return {"schedule": "persistent" if sc.value == self.PERSISTENT else "per-pass",
-                "variants": {n: int(v[i]) for i, n in enumerate(self.PASS_NAMES)}}
+        check(_lib.lib().loop_batch_get_config(self._plan, ctypes.byref(sc), v, ctypes.byref(ns)),
+              "loop_batch_get_config")
+        name = ("per-pass", "persistent", f"streams-{ns.value}")[sc.value]
+        return {"schedule": name, "variants": {n: int(v[i]) for i, n in enumerate(self.PASS_NAMES)}}
 
     def autotune(self, pool, T, reps=20) -> dict:
-        """Time every usable kernel variant of every pass and both schedules on this state
+        """Time every usable kernel variant of every pass and every schedule on this state
         (pool and T are left unchanged) and keep the fastest (see loop_batch_autotune).
         Returns the timings in microseconds and the chosen configuration."""
         self._check_state(pool, T)
-        n = 5 * self.VARIANTS + 2
+        n = 5 * self.VARIANTS + 5
         rep = (ctypes.c_double * n)()
         check(_lib.lib().loop_batch_autotune(self._plan, _ptr(T), _ptr(pool), int(reps), rep, _ptr(self.ws),
                                              self.ws.numel(), _stream_ptr()),
@@ -255,7 +260,8 @@ class Batch:
                             if rep[i * self.VARIANTS + v] >= 0}
         out = self.config()
         out["pass_us"] = passes
-        out["step_us"] = {"per-pass": round(rep[n - 2], 3), "persistent": round(rep[n - 1], 3)}
+        names = ("per-pass", "persistent", "streams-2", "streams-3", "streams-4")
+        out["step_us"] = {name: round(rep[5 * self.VARIANTS + i], 3) for i, name in enumerate(names)}
         return out
 
     def _check_state(self, pool, T):

@@ -154,6 +154,11 @@ template <> struct Plan<256, 8>   { static constexpr int S = 3; static constexpr
 template <> struct Plan<512, 8>   { static constexpr int S = 3; static constexpr int R[4] = {8, 8, 8, 0}; };
 template <> struct Plan<1024, 8>  { static constexpr int S = 4; static constexpr int R[4] = {8, 8, 8, 2}; };
 template <> struct Plan<1024, 16> { static constexpr int S = 3; static constexpr int R[4] = {16, 8, 8, 0}; };
+// Four points per thread (short row transforms spread over more threads).
+template <> struct Plan<8, 4>     { static constexpr int S = 2; static constexpr int R[4] = {4, 2, 0, 0}; };
+template <> struct Plan<16, 4>    { static constexpr int S = 2; static constexpr int R[4] = {4, 4, 0, 0}; };
+template <> struct Plan<32, 4>    { static constexpr int S = 3; static constexpr int R[4] = {4, 4, 2, 0}; };
+template <> struct Plan<64, 4>    { static constexpr int S = 3; static constexpr int R[4] = {4, 4, 4, 0}; };
 
 template <int N>
 constexpr int xlen() {  // padded exchange length

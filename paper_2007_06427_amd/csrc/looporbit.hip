@@ -417,16 +417,23 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
 struct RagVariant {
     int lo, hi;  // transform sizes compiled in: powers of two in [lo, hi]
     bool dma;    // row tiles copied straight into LDS
+    int pt;      // points per thread of the row transforms (0: the default, 8)
 };
-constexpr int kRagVariants = 3;
+constexpr int kRowVariants = 4, kColVariants = 3, kRagVariants = 4;
 __host__ __device__ constexpr bool is_row_pass(int pass) { return pass == PASS_B || pass == PASS_D; }
+__host__ __device__ constexpr int rag_count(int pass) { return is_row_pass(pass) ? kRowVariants : kColVariants; }
 __host__ __device__ constexpr RagVariant rag_variant(int pass, int v) {
-    return is_row_pass(pass) ? (v == 0   ? RagVariant{8, 512, false}
-                                : v == 1 ? RagVariant{8, 64, false}
-                                         : RagVariant{8, 64, true})
-                             : (v == 0   ? RagVariant{8, 1024, false}
-                                : v == 1 ? RagVariant{8, 64, false}
-                                         : RagVariant{8, 512, false});
+    return is_row_pass(pass) ? (v == 0   ? RagVariant{8, 512, false, 0}
+                                : v == 1 ? RagVariant{8, 64, false, 0}
+                                : v == 2 ? RagVariant{8, 64, true, 0}
+                                         : RagVariant{8, 64, false, 4})
+                             : (v == 0   ? RagVariant{8, 1024, false, 0}
+                                : v == 1 ? RagVariant{8, 64, false, 0}
+                                         : RagVariant{8, 512, false, 0});
+}
+template <int M, int PT>
+constexpr int row_pt() {
+    return PT ? PT : RowG<M>::PT;
 }
 
 // Calls f(std::integral_constant<int, S>) for the power of two S == n in [LO, HI]; other n do
@@ -454,8 +461,10 @@ __global__ __launch_bounds__(kBlock) void k_rag(BatchArgs a, const uint32_t* __r
     if constexpr (PASS == PASS_A) {
         size_switch<var.lo, var.hi>(sh.N, [&](auto c) { col_pass_A<decltype(c)::value>(sh, tile, w, lds, a.tw); });
     } else if constexpr (PASS == PASS_B) {
-        size_switch<var.lo, var.hi>(
-            sh.M, [&](auto c) { row_pass_B<decltype(c)::value, var.dma>(sh, tile, w, lds, a.tw); });
+        size_switch<var.lo, var.hi>(sh.M, [&](auto c) {
+            constexpr int M_ = decltype(c)::value;
+            row_pass_B<M_, var.dma, row_pt<M_, var.pt>()>(sh, tile, w, lds, a.tw);
+        });
     } else if constexpr (PASS == PASS_C) {
         size_switch<var.lo, var.hi>(sh.N, [&](auto c) {
             col_pass_C<decltype(c)::value>(sh, tile, a.T + l, w, MODE_STEP, a.dtau, a.scheme, lds, red, a.tw);
@@ -463,8 +472,9 @@ __global__ __launch_bounds__(kBlock) void k_rag(BatchArgs a, const uint32_t* __r
     } else if constexpr (PASS == PASS_D) {
         double* jh = a.J_hist ? a.J_hist + (size_t)s * a.nloops + l : nullptr;
         size_switch<var.lo, var.hi>(sh.M, [&](auto c) {
-            row_pass_D<decltype(c)::value, var.dma>(sh, tile, w, a.T + l, MODE_STEP, a.dtau, jh, nullptr, nullptr,
-                                                    lds, a.tw);
+            constexpr int M_ = decltype(c)::value;
+            row_pass_D<M_, var.dma, row_pt<M_, var.pt>()>(sh, tile, w, a.T + l, MODE_STEP, a.dtau, jh, nullptr,
+                                                          nullptr, lds, a.tw);
         });
     } else {
         size_switch<var.lo, var.hi>(sh.N, [&](auto c) {
@@ -478,7 +488,11 @@ void launch_rag(int v, dim3 grid, size_t lds, hipStream_t hs, const BatchArgs& a
     switch (v) {
         case 0: hipLaunchKernelGGL((k_rag<PASS, 0>), grid, dim3(kBlock), lds, hs, a, c, step); break;
         case 1: hipLaunchKernelGGL((k_rag<PASS, 1>), grid, dim3(kBlock), lds, hs, a, c, step); break;
-        default: hipLaunchKernelGGL((k_rag<PASS, 2>), grid, dim3(kBlock), lds, hs, a, c, step); break;
+        case 2: hipLaunchKernelGGL((k_rag<PASS, 2>), grid, dim3(kBlock), lds, hs, a, c, step); break;
+        default:
+            if constexpr (is_row_pass(PASS))
+                hipLaunchKernelGGL((k_rag<PASS, 3>), grid, dim3(kBlock), lds, hs, a, c, step);
+            break;
     }
 }
 
@@ -927,8 +941,15 @@ struct BatchPlan {
     int pass_off[6] = {0, 0, 0, 0, 0, 0};
     int schedule = 0;                  // LOOP_BATCH_PER_PASS or LOOP_BATCH_PERSISTENT
     int variant[5] = {0, 0, 0, 0, 0};  // k_rag variant of each pass
-    size_t pass_lds[5] = {0, 0, 0, 0, 0};  // dynamic LDS of each pass's launches
+    size_t pass_lds[5][kRagVariants] = {};  // dynamic LDS of each pass's launches, per variant
     int min_m = 1 << 30, max_m = 0, min_n = 1 << 30, max_n2 = 0;  // transform sizes present
+    // multi-stream schedule: for K = 2, 3, 4 groups of about equal work, the tiles of each
+    // group and pass; group g > 0 runs on the plan's stream sx[g - 1] (default priority)
+    int nstreams = 2;
+    uint32_t* d_group_codes = nullptr;
+    int group_off[3][4][6] = {};  // [K - 2][group][pass .. pass + 1]
+    hipStream_t sx[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_lag[3] = {nullptr, nullptr, nullptr}, ev_join[3] = {nullptr, nullptr, nullptr};
 };
 
 int col_tiles(const Shape& s) { return (s.C + 2048 / s.N - 1) / (2048 / s.N); }
@@ -942,11 +963,20 @@ size_t pass_lds_bytes(const Shape& s) {
     const size_t row = std::max<size_t>(2 * (size_t)cmax * (rows + 1), 2304);
     return std::max(col, row) * sizeof(cd);
 }
-// Dynamic LDS of one pass of the launch-per-pass form for a loop of this shape.
-size_t rag_lds_bytes(const Shape& s, int pass) {
+// Dynamic LDS of one pass of the launch-per-pass form for a loop of this shape (row passes:
+// with 8 or 4 points per thread).
+size_t rag_lds_bytes(const Shape& s, int pass, int pt) {
     size_t n = 0;
     auto row = [&](auto c) {
-        using G = RowG<decltype(c)::value>;
+        constexpr int M_ = decltype(c)::value;
+        if constexpr (M_ <= 64) {
+            if (pt == 4) {
+                using G = RowG<M_, 4>;
+                n = pass == PASS_B ? G::LDS_B : G::LDS;
+                return;
+            }
+        }
+        using G = RowG<M_>;
         n = pass == PASS_B ? G::LDS_B : G::LDS;
     };
     auto col = [&](auto c) { n = ColG<decltype(c)::value>::LDS; };
@@ -957,7 +987,7 @@ size_t rag_lds_bytes(const Shape& s, int pass) {
     return n * sizeof(cd);
 }
 bool rag_covers(const BatchPlan* p, int pass, int v) {
-    if (v < 0 || v >= kRagVariants) return false;
+    if (v < 0 || v >= rag_count(pass)) return false;
     const RagVariant r = rag_variant(pass, v);
     const int lo = is_row_pass(pass) ? p->min_m : p->min_n, hi = is_row_pass(pass) ? p->max_m : p->max_n2;
     return r.lo <= lo && hi <= r.hi;
@@ -965,9 +995,9 @@ bool rag_covers(const BatchPlan* p, int pass, int v) {
 // The narrowest staged variant covering the plan's sizes.
 int rag_default(const BatchPlan* p, int pass) {
     int best = 0;
-    for (int v = 0; v < kRagVariants; ++v) {
+    for (int v = 0; v < rag_count(pass); ++v) {
         const RagVariant r = rag_variant(pass, v), b = rag_variant(pass, best);
-        if (!r.dma && rag_covers(p, pass, v) && r.hi - r.lo < b.hi - b.lo) best = v;
+        if (!r.dma && !r.pt && rag_covers(p, pass, v) && r.hi - r.lo < b.hi - b.lo) best = v;
     }
     return best;
 }
@@ -980,6 +1010,13 @@ void free_plan(BatchPlan* p) {
     if (p->d_loops) hipFree(p->d_loops);
     if (p->d_items) hipFree(p->d_items);
     if (p->d_pass_codes) hipFree(p->d_pass_codes);
+    if (p->d_group_codes) hipFree(p->d_group_codes);
+    if (p->ev_fork) hipEventDestroy(p->ev_fork);
+    for (int k = 0; k < 3; ++k) {
+        if (p->ev_lag[k]) hipEventDestroy(p->ev_lag[k]);
+        if (p->ev_join[k]) hipEventDestroy(p->ev_join[k]);
+        if (p->sx[k]) hipStreamDestroy(p->sx[k]);
+    }
     hipSetDevice(dev0);
     delete p;
 }
@@ -997,7 +1034,7 @@ unsigned elem_blocks(size_t n) {
 // Configurations chosen by loop_batch_autotune, per device and multiset of (Nx, Ns), for
 // the plans created later in the process.
 struct TunedConfig {
-    int schedule;
+    int schedule, nstreams;
     int variant[5];
 };
 std::mutex g_tune_mu;
@@ -1235,7 +1272,9 @@ int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns,
         p->max_h = std::max(p->max_h, b.sh.H);
         p->lds_bytes = std::max(p->lds_bytes, pass_lds_bytes(b.sh));
         for (int pass = PASS_A; pass <= PASS_E; ++pass)
-            p->pass_lds[pass] = std::max(p->pass_lds[pass], rag_lds_bytes(b.sh, pass));
+            for (int v = 0; v < rag_count(pass); ++v)
+                p->pass_lds[pass][v] =
+                    std::max(p->pass_lds[pass][v], rag_lds_bytes(b.sh, pass, rag_variant(pass, v).pt));
         p->min_m = std::min(p->min_m, b.sh.M);
         p->max_m = std::max(p->max_m, b.sh.M);
         p->min_n = std::min(p->min_n, b.sh.N);
@@ -1247,6 +1286,7 @@ int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns,
         const auto it = tune_cache().find(plan_signature(p));
         if (it != tune_cache().end()) {
             p->schedule = it->second.schedule;
+            p->nstreams = it->second.nstreams;
             for (int pass = PASS_A; pass <= PASS_E; ++pass) p->variant[pass] = it->second.variant[pass];
         }
     }
@@ -1274,6 +1314,29 @@ int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns,
             for (int t = 0; t < p->loops[l].nt[pass]; ++t) pcodes.push_back(item_code(l, pass, t));
     }
     p->pass_off[5] = (int)pcodes.size();
+    // multi-stream schedule: K groups of about equal bytes per step (larger loops placed first,
+    // each on the lightest group so far), for K = 2, 3, 4
+    std::vector<uint32_t> gcodes;
+    for (int K = 2; K <= 4; ++K) {
+        std::vector<int> group(nloops, 0);
+        size_t load[4] = {0, 0, 0, 0};
+        for (int l : order) {
+            const Shape& sh = p->loops[l].sh;
+            int g = 0;
+            for (int h = 1; h < K; ++h)
+                if (load[h] < load[g]) g = h;
+            group[l] = g;
+            load[g] += 9 * (size_t)sh.C * sh.N + 4 * (size_t)sh.C * sh.NB;
+        }
+        for (int g = 0; g < K; ++g)
+            for (int pass = PASS_A; pass <= PASS_E; ++pass) {
+                p->group_off[K - 2][g][pass] = (int)gcodes.size();
+                for (int l : order)
+                    if (group[l] == g)
+                        for (int t = 0; t < p->loops[l].nt[pass]; ++t) gcodes.push_back(item_code(l, pass, t));
+                p->group_off[K - 2][g][pass + 1] = (int)gcodes.size();
+            }
+    }
     // one resident wave of blocks
     int per_cu = 1, cus = 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBlock, p->lds_bytes) != hipSuccess ||
@@ -1288,17 +1351,28 @@ int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns,
         hipMemcpy(p->d_items, items.data(), sizeof(uint32_t) * items.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMalloc((void**)&p->d_pass_codes, sizeof(uint32_t) * pcodes.size()) != hipSuccess ||
         hipMemcpy(p->d_pass_codes, pcodes.data(), sizeof(uint32_t) * pcodes.size(), hipMemcpyHostToDevice) !=
-            hipSuccess) {
+            hipSuccess ||
+        hipMalloc((void**)&p->d_group_codes, sizeof(uint32_t) * gcodes.size()) != hipSuccess ||
+        hipMemcpy(p->d_group_codes, gcodes.data(), sizeof(uint32_t) * gcodes.size(), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess) {
         free_plan(p);
         return LOOP_EHIP;
     }
+    for (int k = 0; k < 3; ++k)
+        if (hipStreamCreateWithFlags(&p->sx[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p->ev_lag[k], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&p->ev_join[k], hipEventDisableTiming) != hipSuccess) {
+            free_plan(p);
+            return LOOP_EHIP;
+        }
     *plan = p;
     return LOOP_OK;
 }
 
 int loop_batch_set_schedule(void* plan, int schedule) {
     BatchPlan* p = static_cast<BatchPlan*>(plan);
-    if (!p || (schedule != LOOP_BATCH_PER_PASS && schedule != LOOP_BATCH_PERSISTENT)) return LOOP_EINVAL;
+    if (!p || schedule < LOOP_BATCH_PER_PASS || schedule > LOOP_BATCH_STREAMS) return LOOP_EINVAL;
     p->schedule = schedule;
     return LOOP_OK;
 }
@@ -1362,17 +1436,56 @@ BatchArgs batch_args(const BatchPlan* p, char* base, double* T, double* J_hist, 
     return a;
 }
 
-void launch_pass(const BatchPlan* p, int pass, int step, const BatchArgs& a, hipStream_t hs) {
-    const dim3 grid(p->pass_off[pass + 1] - p->pass_off[pass]);
-    const uint32_t* c = p->d_pass_codes + p->pass_off[pass];
+// One pass over the tiles c[0 .. n) with the plan's variant for that pass.
+void launch_pass_codes(const BatchPlan* p, int pass, int step, const BatchArgs& a, hipStream_t hs,
+                       const uint32_t* c, int n) {
+    if (n == 0) return;
+    const dim3 grid(n);
     const int v = p->variant[pass];
-    const size_t lds = p->pass_lds[pass];
+    const size_t lds = p->pass_lds[pass][v];
     switch (pass) {
         case PASS_A: launch_rag<PASS_A>(v, grid, lds, hs, a, c, step); break;
         case PASS_B: launch_rag<PASS_B>(v, grid, lds, hs, a, c, step); break;
         case PASS_C: launch_rag<PASS_C>(v, grid, lds, hs, a, c, step); break;
         case PASS_D: launch_rag<PASS_D>(v, grid, lds, hs, a, c, step); break;
         default: launch_rag<PASS_E>(v, grid, lds, hs, a, c, step); break;
+    }
+}
+
+void launch_pass(const BatchPlan* p, int pass, int step, const BatchArgs& a, hipStream_t hs) {
+    launch_pass_codes(p, pass, step, a, hs, p->d_pass_codes + p->pass_off[pass],
+                      p->pass_off[pass + 1] - p->pass_off[pass]);
+}
+
+void launch_group_pass(const BatchPlan* p, int g, int pass, int step, const BatchArgs& a, hipStream_t hs) {
+    const int* off = p->group_off[p->nstreams - 2][g];
+    launch_pass_codes(p, pass, step, a, hs, p->d_group_codes + off[pass], off[pass + 1] - off[pass]);
+}
+
+// Multi-stream schedule: group 0 on the caller's stream, group g > 0 on the plan's stream
+// sx[g - 1], each group started one pass after the previous one (after its first pass B), so
+// that the GPU runs different passes of different groups side by side, each as its own
+// kernel with its own registers and LDS. Events fork the plan's streams from the caller's and
+// join them back before the caller's next work.
+void launch_streams(const BatchPlan* p, int nsteps, const BatchArgs& a, hipStream_t hs) {
+    const int K = p->nstreams;
+    auto st = [&](int g) { return g == 0 ? hs : p->sx[g - 1]; };
+    hipEventRecord(p->ev_fork, hs);
+    for (int g = 1; g < K; ++g) hipStreamWaitEvent(st(g), p->ev_fork, 0);
+    for (int g = 0; g < K; ++g) {
+        if (g > 0) hipStreamWaitEvent(st(g), p->ev_lag[g - 1], 0);
+        launch_group_pass(p, g, PASS_A, 0, a, st(g));
+        launch_group_pass(p, g, PASS_B, 0, a, st(g));
+        if (g + 1 < K) hipEventRecord(p->ev_lag[g], st(g));
+    }
+    // queue the groups' launches in turn, one pass each
+    for (int i = 0; i < nsteps; ++i)
+        for (int pass = PASS_B; pass <= PASS_E; ++pass)
+            for (int g = 0; g < K; ++g)
+                if (!(i == 0 && pass == PASS_B)) launch_group_pass(p, g, pass, i, a, st(g));
+    for (int g = 1; g < K; ++g) {
+        hipEventRecord(p->ev_join[g - 1], st(g));
+        hipStreamWaitEvent(hs, p->ev_join[g - 1], 0);
     }
 }
 }  // namespace
@@ -1431,6 +1544,8 @@ int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau,
             const long long total = (long long)p->nA + (long long)nsteps * p->ips;
             if (total >= (1ll << 31)) return LOOP_EINVAL;
             hipLaunchKernelGGL(k_batch, dim3(p->grid), dim3(kBlock), p->lds_bytes, hs, a);
+        } else if (p->schedule == LOOP_BATCH_STREAMS) {
+            launch_streams(p, nsteps, a, hs);
         } else {
             launch_pass(p, PASS_A, 0, a, hs);
             for (int i = 0; i < nsteps; ++i)
@@ -1440,6 +1555,13 @@ int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau,
     return loop_batch_store(plan, uhat_pool, ws, ws_bytes, stream);
 }
 
+int loop_batch_set_streams(void* plan, int nstreams) {
+    BatchPlan* p = static_cast<BatchPlan*>(plan);
+    if (!p || nstreams < 2 || nstreams > 4) return LOOP_EINVAL;
+    p->nstreams = nstreams;
+    return LOOP_OK;
+}
+
 int loop_batch_set_variant(void* plan, int pass, int variant) {
     BatchPlan* p = static_cast<BatchPlan*>(plan);
     if (!p || pass < PASS_A || pass > PASS_E || !rag_covers(p, pass, variant)) return LOOP_EINVAL;
@@ -1447,10 +1569,11 @@ int loop_batch_set_variant(void* plan, int pass, int variant) {
     return LOOP_OK;
 }
 
-int loop_batch_get_config(const void* plan, int* schedule, int* variants) {
+int loop_batch_get_config(const void* plan, int* schedule, int* variants, int* nstreams) {
     const BatchPlan* p = static_cast<const BatchPlan*>(plan);
     if (!p) return LOOP_EINVAL;
     if (schedule) *schedule = p->schedule;
+    if (nstreams) *nstreams = p->nstreams;
     if (variants)
         for (int pass = PASS_A; pass <= PASS_E; ++pass) variants[pass] = p->variant[pass];
     return LOOP_OK;
@@ -1487,7 +1610,7 @@ int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, in
         release();
         return LOOP_EHIP;
     }
-    std::vector<double> rep(5 * kRagVariants + 2, -1.0);
+    std::vector<double> rep(5 * kRagVariants + 5, -1.0);
     // Mean microseconds per call of `launch` over n back-to-back calls, best of three trials.
     auto time_calls = [&](auto&& launch, int n) -> double {
         double best = 1e300;
@@ -1510,7 +1633,7 @@ int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, in
     for (int pass = PASS_A; pass <= PASS_E; ++pass) {
         int best_v = p->variant[pass];
         double best_t = 1e300;
-        for (int v = 0; v < kRagVariants; ++v) {
+        for (int v = 0; v < rag_count(pass); ++v) {
             if (!rag_covers(p, pass, v)) continue;
             p->variant[pass] = v;
             launch_pass(p, pass, 0, a, hs);  // the first launch of a kernel also loads its code
@@ -1523,15 +1646,27 @@ int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, in
         }
         p->variant[pass] = best_v;
     }
-    double sched_us[2];
-    for (int sc = LOOP_BATCH_PER_PASS; sc <= LOOP_BATCH_PERSISTENT; ++sc) {
+    // schedules: per-pass, persistent, then the multi-stream one with 2, 3 and 4 streams
+    double best_us = 1e300;
+    int best_s = LOOP_BATCH_PER_PASS, best_k = 2;
+    for (int c = 0; c < 5; ++c) {
+        const int sc = c < 2 ? c : LOOP_BATCH_STREAMS, k = c < 2 ? 2 : c;
         p->schedule = sc;
+        p->nstreams = k;
         loop_batch_step(p, tT, tpool, dtau, scheme, 1, nullptr, ws, ws_bytes, stream);
-        sched_us[sc] = time_calls([&] { loop_batch_step(p, tT, tpool, dtau, scheme, reps, nullptr, ws, ws_bytes, stream); }, 1) / reps;
-        rep[5 * kRagVariants + sc] = sched_us[sc];
+        const double us =
+            time_calls([&] { loop_batch_step(p, tT, tpool, dtau, scheme, reps, nullptr, ws, ws_bytes, stream); },
+                       1) /
+            reps;
+        rep[5 * kRagVariants + c] = us;
+        if (us < best_us) {
+            best_us = us;
+            best_s = sc;
+            best_k = k;
+        }
     }
-    p->schedule = sched_us[LOOP_BATCH_PERSISTENT] < sched_us[LOOP_BATCH_PER_PASS] ? LOOP_BATCH_PERSISTENT
-                                                                                 : LOOP_BATCH_PER_PASS;
+    p->schedule = best_s;
+    p->nstreams = best_k;
     st = last_error();
     if (hipStreamSynchronize(hs) != hipSuccess) st = LOOP_EHIP;
     release();
@@ -1541,6 +1676,7 @@ int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, in
     if (report) std::copy(rep.begin(), rep.end(), report);
     TunedConfig c;
     c.schedule = p->schedule;
+    c.nstreams = p->nstreams;
     for (int pass = PASS_A; pass <= PASS_E; ++pass) c.variant[pass] = p->variant[pass];
     std::lock_guard<std::mutex> g(g_tune_mu);
     tune_cache()[plan_signature(p)] = c;

@@ -292,9 +292,9 @@ __device__ __forceinline__ void col_pass_E(const Shape& sh, int block, const Wor
 // TPF = M/PT threads per row transform, P = kBlock / TPF pairs of rows per block, thread
 // tid -> t = tid % TPF, p = tid / TPF. A block covers ROWS = 2P consecutive global rows
 // g0 .. g0 + 2P - 1 (g = l * N + n, loop-major), paired as (g0 + p, g0 + P + p).
-template <int M>
+template <int M, int PT_ = (M >= 1024 ? 16 : 8)>
 struct RowG {
-    static constexpr int PT = M >= 1024 ? 16 : 8;
+    static constexpr int PT = PT_;
     static constexpr int TPF = M / PT;  // <= 64: one transform per wavefront at most
     static constexpr int P = kBlock / TPF;
     static constexpr int ROWS = 2 * P;
@@ -310,34 +310,46 @@ struct RowG {
 };
 
 // Load rows [g0, g0 + ROWS) of NT intermediates X[0..NT) into tiles tile + i * TILE, laid
-// out [j][r] with stride TS, coalesced along n. Rows past nrows read as zero. Every global
-// load is issued before the first LDS store, so the loads of a tile are in flight together.
-// ROWS and N are powers of two.
+// out [j][r] with stride TS, coalesced along n. Rows past nrows read as zero. issue() puts
+// every global load of the tile in flight (into registers); commit() stores them to LDS, so
+// a caller can do other work while the loads travel. ROWS and N are powers of two.
+template <int ROWS, int CMAX, int TS, int TILE, int NT>
+struct RowTiles {
+    static constexpr int NL = (ROWS * CMAX + kBlock - 1) / kBlock;
+    cd buf[NT][NL];
+    __device__ __forceinline__ void issue(const cd* const (&X)[NT], size_t g0, const Shape& sh, size_t nrows) {
+        const int n = ROWS * sh.C;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int i = threadIdx.x + k * kBlock;
+            const int j = i / ROWS, r = i % ROWS;
+            const size_t g = g0 + r;
+            const bool ok = i < n && g < nrows;
+            const size_t off = ok ? ((g >> sh.logN) * sh.C + j) * sh.N + (g & (size_t)(sh.N - 1)) : 0;
+#pragma unroll
+            for (int q = 0; q < NT; ++q) buf[q][k] = ok ? X[q][off] : cd{0.0, 0.0};
+        }
+    }
+    __device__ __forceinline__ void commit(cd* tile, const Shape& sh) const {
+        const int n = ROWS * sh.C;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int i = threadIdx.x + k * kBlock;
+            if (i < n) {
+                const int j = i / ROWS, r = i % ROWS;
+#pragma unroll
+                for (int q = 0; q < NT; ++q) tile[q * TILE + j * TS + r] = buf[q][k];
+            }
+        }
+    }
+};
+
 template <int ROWS, int CMAX, int TS, int TILE, int NT>
 __device__ __forceinline__ void load_rows(cd* tile, const cd* const (&X)[NT], size_t g0, const Shape& sh,
                                           size_t nrows) {
-    constexpr int NL = (ROWS * CMAX + kBlock - 1) / kBlock;
-    const int n = ROWS * sh.C;
-    cd buf[NT][NL];
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        const int i = threadIdx.x + k * kBlock;
-        const int j = i / ROWS, r = i % ROWS;
-        const size_t g = g0 + r;
-        const bool ok = i < n && g < nrows;
-        const size_t off = ok ? ((g >> sh.logN) * sh.C + j) * sh.N + (g & (size_t)(sh.N - 1)) : 0;
-#pragma unroll
-        for (int q = 0; q < NT; ++q) buf[q][k] = ok ? X[q][off] : cd{0.0, 0.0};
-    }
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        const int i = threadIdx.x + k * kBlock;
-        if (i < n) {
-            const int j = i / ROWS, r = i % ROWS;
-#pragma unroll
-            for (int q = 0; q < NT; ++q) tile[q * TILE + j * TS + r] = buf[q][k];
-        }
-    }
+    RowTiles<ROWS, CMAX, TS, TILE, NT> ld;
+    ld.issue(X, g0, sh, nrows);
+    ld.commit(tile, sh);
 }
 
 // The same tiles as load_rows, copied by the load unit straight into LDS
@@ -345,9 +357,10 @@ __device__ __forceinline__ void load_rows(cd* tile, const cd* const (&X)[NT], si
 // base + 16 i). One wavefront instruction moves 64 consecutive rows of one column j to
 // tile[j][r0 .. r0 + 63], so ROWS must be a multiple of 64. Nothing passes through vector
 // registers. Lanes whose row lies past nrows store zeros with ordinary LDS writes instead.
-// The wavefront waits for its own copies before returning; the caller's barrier then makes
-// every wavefront's copies visible to the block.
-template <int ROWS, int CMAX, int TS, int TILE, int NT>
+// With WAIT the wavefront waits for its own copies before returning (otherwise the caller
+// waits for vmcnt(0) itself); the caller's barrier then makes every wavefront's copies
+// visible to the block.
+template <int ROWS, int CMAX, int TS, int TILE, int NT, bool WAIT = true>
 __device__ __forceinline__ void load_rows_lds(cd* tile, const cd* const (&X)[NT], size_t g0, const Shape& sh,
                                               size_t nrows) {
     static_assert(ROWS % 64 == 0, "a copy instruction covers 64 rows of one column");
@@ -368,7 +381,7 @@ __device__ __forceinline__ void load_rows_lds(cd* tile, const cd* const (&X)[NT]
             dst[lane] = cd{0.0, 0.0};
         }
     }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if constexpr (WAIT) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
 template <int ROWS, int CMAX>
@@ -403,10 +416,10 @@ __device__ __forceinline__ cd pack2(cd f, cd g) { return cd{f.x - g.y, f.y + g.x
 // of the larger (r_x can exceed u by q_max^5) swamp the smaller. Then one forward transform
 // of (f_a g_a) + i (f_b g_b) and the split into the two rows' half spectra (scaled by 1/M),
 // written to tile[j][r] over the inputs' LDS.
-template <int M>
+template <int M, int PT = RowG<M>::PT>
 __device__ __forceinline__ void row_products(const Shape& sh, cd* va, cd* vb, cd* lds, int t, int p,
-                                             const TwCache<M, RowG<M>::PT>& twc) {
-    using G = RowG<M>;
+                                             const TwCache<M, PT>& twc) {
+    using G = RowG<M, PT>;
     cd* ex = lds + p * xlen<M>();
     __syncthreads();  // every wave has read its inputs from the tiles: the tiles are free
     fft<M, G::PT, true>(va, t, ex, twc);
@@ -449,36 +462,51 @@ __device__ __forceinline__ void row_products(const Shape& sh, cd* va, cd* vb, cd
     __syncthreads();
 }
 
-// DMA selects load_rows_lds over load_rows (tiles of 64 rows or more).
-template <int M, bool DMA = false>
+// DMA selects load_rows_lds over load_rows (tiles of 64 rows or more). PT below the default
+// spreads each row transform over more threads: tiles are then shorter, and a block covers
+// the rows of one default-size tile (so that tile indices keep their meaning) in SUB
+// consecutive sub-tiles.
+template <int M, bool DMA = false, int PT = RowG<M>::PT>
 __device__ __forceinline__ void row_pass_B(const Shape& sh, int block, const Work& w, cd* lds,
                                            const cd* __restrict__ tw) {
-    using G = RowG<M>;
+    using G = RowG<M, PT>;
+    constexpr int SUB = RowG<M>::ROWS / G::ROWS;
     const size_t nrows = (size_t)sh.nloops * sh.N;
-    const size_t g0 = (size_t)block * G::ROWS;
     const int t = threadIdx.x % G::TPF, p = threadIdx.x / G::TPF;
-    TwCache<M, G::PT> twc;
-    tw_cache_load<M, G::PT>(twc, t, tw);
-    {
-        const cd* const src[1] = {w.A};
-        if constexpr (DMA)
-            load_rows_lds<G::ROWS, G::CMAX, G::TS, G::TILE, 1>(lds, src, g0, sh, nrows);
-        else
-            load_rows<G::ROWS, G::CMAX, G::TS, G::TILE, 1>(lds, src, g0, sh, nrows);
-    }
-    __syncthreads();
+    TwCache<M, PT> twc;
+    tw_cache_load<M, PT>(twc, t, tw);
     const double dq = kTwoPi / sh.L;
-    cd va[G::PT], vb[G::PT];
+    auto sub = [&](size_t g0) {
+        {
+            const cd* const src[1] = {w.A};
+            if constexpr (DMA)
+                load_rows_lds<G::ROWS, G::CMAX, G::TS, G::TILE, 1>(lds, src, g0, sh, nrows);
+            else
+                load_rows<G::ROWS, G::CMAX, G::TS, G::TILE, 1>(lds, src, g0, sh, nrows);
+        }
+        __syncthreads();
+        cd va[PT], vb[PT];
 #pragma unroll
-    for (int m = 0; m < G::PT; ++m) {
-        const int e = t + m * G::TPF;
-        const double q = dq * (double)((e <= M / 2) ? e : e - M);
-        const cd a = herm_ext(lds, G::TS, p, e, M, sh.Kx), b = herm_ext(lds, G::TS, G::P + p, e, M, sh.Kx);
-        va[m] = pack2(a, b);                                           // u, rows a and b
-        vb[m] = pack2(cd{-q * a.y, q * a.x}, cd{-q * b.y, q * b.x});  // u_x = (i q u_hat), rows a and b
+        for (int m = 0; m < PT; ++m) {
+            const int e = t + m * G::TPF;
+            const double q = dq * (double)((e <= M / 2) ? e : e - M);
+            const cd a = herm_ext(lds, G::TS, p, e, M, sh.Kx), b = herm_ext(lds, G::TS, G::P + p, e, M, sh.Kx);
+            va[m] = pack2(a, b);                                           // u, rows a and b
+            vb[m] = pack2(cd{-q * a.y, q * a.x}, cd{-q * b.y, q * b.x});  // u_x = (i q u_hat), rows a and b
+        }
+        row_products<M, PT>(sh, va, vb, lds, t, p, twc);
+        store_rows<G::ROWS, G::CMAX>(lds, G::TS, w.BD, g0, sh, nrows);
+    };
+    const size_t gb = (size_t)block * RowG<M>::ROWS;
+    if constexpr (SUB == 1) {
+        sub(gb);
+    } else {
+#pragma unroll 1
+        for (int h = 0; h < SUB; ++h) {
+            if (h > 0) __syncthreads();  // the previous sub-tile's output tile has been stored
+            sub(gb + (size_t)h * G::ROWS);
+        }
     }
-    row_products<M>(sh, va, vb, lds, t, p, twc);
-    store_rows<G::ROWS, G::CMAX>(lds, G::TS, w.BD, g0, sh, nrows);
 }
 
 // Sum the per-column partials of loop l into J, dJ/dT; in MODE_STEP also advance T.
@@ -514,41 +542,62 @@ __device__ __forceinline__ void finalize_loop(const Shape& sh, int l, const Work
     if (bad) atomicCAS(w.status, 0, -4);
 }
 
-template <int M, bool DMA = false>
+template <int M, bool DMA = false, int PT = RowG<M>::PT>
 __device__ __forceinline__ void row_pass_D(const Shape& sh, int block, const Work& w, double* T, int mode,
                                            double dtau, double* J_hist, double* Jout, double* dJdTout, cd* lds,
                                            const cd* __restrict__ tw) {
-    using G = RowG<M>;
+    using G = RowG<M, PT>;
+    constexpr int SUB = RowG<M>::ROWS / G::ROWS;
     const size_t nrows = (size_t)sh.nloops * sh.N;
-    const size_t g0 = (size_t)block * G::ROWS;
-    // loops whose first row lies in this block are finished here (partials from pass C)
-    if (threadIdx.x < 64) {
-        const size_t l0 = (g0 + sh.N - 1) >> sh.logN;  // first loop starting at or after g0
-        for (size_t l = l0; (l << sh.logN) < g0 + G::ROWS && l < (size_t)sh.nloops; ++l)
-            finalize_loop(sh, (int)l, w, T, mode, dtau, J_hist, Jout, dJdTout);
-    }
+    const size_t gb = (size_t)block * RowG<M>::ROWS;
+    // Loops whose first row lies in this block are finished here (partials from pass C), by
+    // wavefront 0 while the first sub-tile's loads are in flight.
+    auto finalize = [&]() {
+        if (threadIdx.x < 64) {
+            const size_t l0 = (gb + sh.N - 1) >> sh.logN;  // first loop starting at or after gb
+            for (size_t l = l0; (l << sh.logN) < gb + RowG<M>::ROWS && l < (size_t)sh.nloops; ++l)
+                finalize_loop(sh, (int)l, w, T, mode, dtau, J_hist, Jout, dJdTout);
+        }
+    };
     cd* tA = lds;
     cd* tC = lds + G::TILE;
     const int t = threadIdx.x % G::TPF, p = threadIdx.x / G::TPF;
-    TwCache<M, G::PT> twc;
-    tw_cache_load<M, G::PT>(twc, t, tw);
-    {
-        const cd* const src[2] = {w.A, w.Cb};
-        if constexpr (DMA)
-            load_rows_lds<G::ROWS, G::CMAX, G::TS, G::TILE, 2>(tA, src, g0, sh, nrows);
-        else
-            load_rows<G::ROWS, G::CMAX, G::TS, G::TILE, 2>(tA, src, g0, sh, nrows);
-    }
-    __syncthreads();
-    cd va[G::PT], vb[G::PT];
+    TwCache<M, PT> twc;
+    tw_cache_load<M, PT>(twc, t, tw);
+    auto sub = [&](size_t g0, bool first) {
+        {
+            const cd* const src[2] = {w.A, w.Cb};
+            if constexpr (DMA) {
+                load_rows_lds<G::ROWS, G::CMAX, G::TS, G::TILE, 2, false>(tA, src, g0, sh, nrows);
+                if (first) finalize();
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            } else {
+                RowTiles<G::ROWS, G::CMAX, G::TS, G::TILE, 2> ld;
+                ld.issue(src, g0, sh, nrows);
+                if (first) finalize();
+                ld.commit(tA, sh);
+            }
+        }
+        __syncthreads();
+        cd va[PT], vb[PT];
 #pragma unroll
-    for (int m = 0; m < G::PT; ++m) {
-        const int e = t + m * G::TPF;
-        va[m] = pack2(herm_ext(tA, G::TS, p, e, M, sh.Kx), herm_ext(tA, G::TS, G::P + p, e, M, sh.Kx));  // u
-        vb[m] = pack2(herm_ext(tC, G::TS, p, e, M, sh.Kx), herm_ext(tC, G::TS, G::P + p, e, M, sh.Kx));  // r_x
+        for (int m = 0; m < PT; ++m) {
+            const int e = t + m * G::TPF;
+            va[m] = pack2(herm_ext(tA, G::TS, p, e, M, sh.Kx), herm_ext(tA, G::TS, G::P + p, e, M, sh.Kx));  // u
+            vb[m] = pack2(herm_ext(tC, G::TS, p, e, M, sh.Kx), herm_ext(tC, G::TS, G::P + p, e, M, sh.Kx));  // r_x
+        }
+        row_products<M, PT>(sh, va, vb, lds, t, p, twc);
+        store_rows<G::ROWS, G::CMAX>(lds, G::TS, w.BD, g0, sh, nrows);
+    };
+    if constexpr (SUB == 1) {
+        sub(gb, true);
+    } else {
+#pragma unroll 1
+        for (int h = 0; h < SUB; ++h) {
+            if (h > 0) __syncthreads();  // the previous sub-tile's output tile has been stored
+            sub(gb + (size_t)h * G::ROWS, h == 0);
+        }
     }
-    row_products<M>(sh, va, vb, lds, t, p, twc);
-    store_rows<G::ROWS, G::CMAX>(lds, G::TS, w.BD, g0, sh, nrows);
 }
 
 }  // namespace lo

@@ -48,12 +48,12 @@ def ragged_specs(n, seed=7):
     return out
 
 
-SCHEDULES = [0, 1]  # per-pass launches, persistent
+SCHEDULES = [0, 1, 2]  # per-pass launches, persistent, two streams
 
 
-def run_batch(api, specs, nsteps, dtau, scheme, schedule=0):
+def run_batch(api, specs, nsteps, dtau, scheme, schedule=0, nstreams=2):
     b = api.Batch([(L, Nx, Ns) for (L, Nx, Ns, T, u) in specs])
-    b.set_schedule(schedule)
+    b.set_schedule(schedule, nstreams)
     pool = b.pack([torch.from_numpy(u) for (*_, u) in specs])
     T = torch.tensor([s[3] for s in specs], dtype=torch.float64, device=DEV)
     Jh = torch.zeros(max(nsteps, 1), len(specs), dtype=torch.float64, device=DEV)
@@ -179,3 +179,24 @@ def test_pass_building_blocks_equal_batch_step(api):
     for i, x in enumerate(b.unpack(pool)):
         assert np.array_equal(x.cpu().numpy(), ub[i])
     assert np.array_equal(T.cpu().numpy(), Tb) and np.array_equal(Jh.cpu().numpy(), Jb)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 13])
+@pytest.mark.parametrize("nstreams", [2, 3, 4])
+def test_stream_schedule_equals_per_pass(api, n, nstreams):
+    """The multi-stream schedule with one loop (its other groups are empty) up to thirteen,
+    over 1 and 4 steps, against the per-pass schedule bit for bit."""
+    specs = ragged_specs(n, seed=21)[:n]
+    for nsteps in (1, 4):
+        _, ua, Ta, Ja = run_batch(api, specs, nsteps, 5e-5, api.IMEX, 0)
+        _, ub, Tb, Jb = run_batch(api, specs, nsteps, 5e-5, api.IMEX, 2, nstreams)
+        for x, y in zip(ua, ub):
+            assert np.array_equal(x, y)
+        assert np.array_equal(Ta, Tb) and np.array_equal(Ja, Jb)
+
+
+def test_set_streams_rejects_counts_outside_2_to_4(api):
+    b = api.Batch([(22.0, 32, 64)])
+    for k in (1, 5):
+        with pytest.raises(api.LoopOrbitError):
+            b.set_schedule(2, k)
