@@ -399,12 +399,16 @@ __device__ __forceinline__ void store_rows(const cd* tile, int TS, cd* X, size_t
     }
 }
 
-// Element e of the Hermitian extension of half spectrum tile[j][r] (j < C; X_0 read as real).
+// Element e of the Hermitian extension of half spectrum tile[j][r] (j < C; X_0 read as real):
+// tile[e] for e <= Kx, conj(tile[M - e]) for e >= M - Kx, zero between. Written without
+// branches (one read of a valid element, then selects), since e differs across the lanes of
+// a transform.
 __device__ __forceinline__ cd herm_ext(const cd* tile, int TS, int r, int e, int M, int Kx) {
-    if (e == 0) return cd{tile[r].x, 0.0};
-    if (e <= Kx) return tile[e * TS + r];
-    if (e >= M - Kx) return cconj(tile[(M - e) * TS + r]);
-    return cd{0.0, 0.0};
+    const int j = e <= M / 2 ? e : M - e;  // |frequency|
+    const bool in = j <= Kx;
+    const cd v = tile[(in ? j : 0) * TS + r];
+    const double y = e == 0 ? 0.0 : (e > M / 2 ? -v.y : v.y);
+    return in ? cd{v.x, y} : cd{0.0, 0.0};
 }
 
 // Spectrum of f + i g for two real rows f, g given by their half spectra (packed complex).
