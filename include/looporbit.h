@@ -108,6 +108,31 @@ int loop_cost_grad(double L, int Nx, int Ns, int nloops, const double* T, const 
 int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau,
               int scheme, int nsteps, double* J_hist, void* ws, size_t ws_bytes, void* stream);
 
+/* Linear extrapolation of whole loops along their trajectory (App. C), in place:
+ *   uhat <- uhat + factor[l] (uhat - uhat_a), T[l] <- T[l] + factor[l] (T[l] - T_a[l]),
+ * for nloops loops in the rfft layout; factor (device, nloops) = 0 leaves a loop unchanged.
+ * Both states should be canonical (as loop_step leaves them); then the result is too. */
+int loop_extrapolate(int Nx, int Ns, int nloops, double* T, double* uhat, const double* T_a,
+                     const double* uhat_a, const double* factor, void* stream);
+
+/* Convergence driver (Sec. 4.3, App. C). Advances the loops with loop_step, `stride` steps
+ * at a time, examining J of every loop on the state after each stride (and the initial one),
+ * until J < J_tol for every loop or max_steps steps. With `accelerate`, each loop also
+ * alternates with linear extrapolations along its trajectory: the first interval starts at
+ * the first examined state with sqrt(J) <= sqrtJ_first (the paper: 1e-3); an interval ends at
+ * the first examined state with sqrt(J) at most half its value at the interval's start, and
+ * the loop is then replaced by l_b + rho/(1 - rho) (l_b - l_a), rho = sqrt(J_b / J_a), from the
+ * interval's end states l_a, l_b; the next interval starts at the extrapolated state.
+ * On return each converged loop holds the state at which it first had J < J_tol (later steps
+ * of the batch do not change it), the others their last state. Host outputs (nloops each):
+ * steps (the step count at convergence, or -1), extrapolations, J_final. Synchronises
+ * `stream` at every examination and allocates its own device buffers (two copies of the
+ * loops); a non-finite J returns LOOP_ENONFINITE. */
+int loop_converge(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau, int scheme,
+                  double J_tol, int stride, long long max_steps, int accelerate, double sqrtJ_first,
+                  long long* steps, int* extrapolations, double* J_final, void* ws, size_t ws_bytes,
+                  void* stream);
+
 /* loop_step runs in one of two forms, with the same results:
  *   resident: one block per loop holds the loop's band state and intermediates in LDS and
  *     takes every step in a single launch; HBM traffic is the state's load and store. It

@@ -154,6 +154,40 @@ def loop_step(uhat: torch.Tensor, T: torch.Tensor, L: float, dtau: float, scheme
     return uhat, T
 
 
+def loop_extrapolate(uhat: torch.Tensor, T: torch.Tensor, uhat_a: torch.Tensor, T_a: torch.Tensor,
+                     factor: torch.Tensor):
+    """In place: (uhat, T) <- (uhat, T) + factor * ((uhat, T) - (uhat_a, T_a)), per loop (App. C)."""
+    nl, Nx, Ns = shape_of(uhat)
+    T = _periods(T, nl, uhat.device)
+    T_a = _periods(T_a, nl, uhat.device)
+    if uhat_a.shape != uhat.shape or uhat_a.dtype != uhat.dtype or not uhat_a.is_contiguous():
+        raise ValueError("uhat_a must match uhat")
+    factor = factor.to(device=uhat.device, dtype=torch.float64).contiguous()
+    if factor.numel() != nl:
+        raise ValueError("factor needs one entry per loop")
+    check(_lib.lib().loop_extrapolate(Nx, Ns, nl, _ptr(T), _ptr(uhat), _ptr(T_a), _ptr(uhat_a), _ptr(factor),
+                                      _stream_ptr()), "loop_extrapolate")
+    return uhat, T
+
+
+def loop_converge(uhat: torch.Tensor, T: torch.Tensor, L: float, dtau: float, scheme: int, J_tol: float,
+                  stride: int = 100, max_steps: int = 10 ** 7, accelerate: bool = True, sqrtJ_first: float = 1e-3,
+                  ws: Workspace = None) -> dict:
+    """Advance the loops in place until J < J_tol (see loop_converge in the C header), with or
+    without the extrapolations of App. C. Returns per-loop steps (-1: not converged),
+    extrapolations and final J."""
+    nl, Nx, Ns = shape_of(uhat)
+    T = _periods(T, nl, uhat.device)
+    ws = ws or workspace(Nx, Ns, nl)
+    steps = (ctypes.c_longlong * nl)()
+    ext = (ctypes.c_int * nl)()
+    Jf = (ctypes.c_double * nl)()
+    check(_lib.lib().loop_converge(float(L), Nx, Ns, nl, _ptr(T), _ptr(uhat), float(dtau), int(scheme), float(J_tol),
+                                   int(stride), int(max_steps), 1 if accelerate else 0, float(sqrtJ_first), steps, ext,
+                                   Jf, ws.ptr, ws.nbytes, _stream_ptr()), "loop_converge")
+    return {"steps": list(steps), "extrapolations": list(ext), "J": list(Jf)}
+
+
 RESIDENT_NEVER, RESIDENT_AUTO, RESIDENT_ALWAYS = 0, 1, 2
 
 

@@ -17,6 +17,10 @@ FLAGS = [
     # packed FP32 instructions are disabled on this target (they are not used by FP64 code anyway)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-value", "-Wno-unused-result",
+    # every product and sum rounded on its own (no fused multiply-add contraction): the same
+    # expression then gives the same bits in every kernel that inlines it, whatever the
+    # surrounding code, so the batched, resident and per-pass forms agree bit for bit
+    "-ffp-contract=off",
 ]
 
 

@@ -192,6 +192,24 @@ __global__ void k_update_T(int nloops, double* T, const double* __restrict__ dJd
     if (l < nloops) T[l] = T[l] - dtau * dJdT[l];
 }
 
+// Linear extrapolation of whole loops along their trajectory (App. C):
+// l <- l + f[l] (l - l_a) for l = (u_hat in rfft layout, T); f = 0 leaves a loop unchanged.
+__global__ __launch_bounds__(256) void k_extrapolate(size_t per_loop, int nloops, cd* __restrict__ u,
+                                                     const cd* __restrict__ ua, double* __restrict__ T,
+                                                     const double* __restrict__ Ta, const double* __restrict__ f) {
+    const size_t total = per_loop * (size_t)nloops;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const double c = f[i / per_loop];
+        if (c != 0.0) {
+            const cd x = u[i], y = ua[i];
+            u[i] = cd{x.x + c * (x.x - y.x), x.y + c * (x.y - y.y)};
+        }
+    }
+    if (blockIdx.x == 0)
+        for (int l = threadIdx.x; l < nloops; l += blockDim.x)
+            if (f[l] != 0.0) T[l] = T[l] + f[l] * (T[l] - Ta[l]);
+}
+
 constexpr uint64_t kWsMagic = 0x4c4f4f504f524254ull;  // "LOOPORBT"
 
 struct WsHeader {
@@ -1192,6 +1210,136 @@ int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, dou
     }
     launch_from_band(s, w.U, u, hs);
     return last_error();
+}
+
+int loop_extrapolate(int Nx, int Ns, int nloops, double* T, double* uhat, const double* T_a, const double* uhat_a,
+                     const double* factor, void* stream) {
+    int st = check_shape(22.0, Nx, Ns, nloops);
+    if (st) return st;
+    if (!aligned(T, 8) || !aligned(uhat, 16) || !aligned(T_a, 8) || !aligned(uhat_a, 16) || !aligned(factor, 8))
+        return LOOP_EINVAL;
+    const size_t per = (size_t)Ns * (Nx / 2 + 1);
+    hipLaunchKernelGGL(k_extrapolate, dim3(elem_blocks(per * nloops)), dim3(256), 0, (hipStream_t)stream, per, nloops,
+                       reinterpret_cast<cd*>(uhat), reinterpret_cast<const cd*>(uhat_a), T, T_a, factor);
+    return last_error();
+}
+
+int loop_converge(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau, int scheme,
+                  double J_tol, int stride, long long max_steps, int accelerate, double sqrtJ_first,
+                  long long* steps, int* extrapolations, double* J_final, void* ws, size_t ws_bytes, void* stream) {
+    int st = check_shape(L, Nx, Ns, nloops);
+    if (st) return st;
+    if (!aligned(T, 8) || !aligned(uhat, 16) || !steps || !extrapolations || !J_final) return LOOP_EINVAL;
+    if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1) || !(J_tol > 0.0) || stride < 1 ||
+        max_steps < 0 || !(sqrtJ_first > 0.0))
+        return LOOP_EINVAL;
+    hipStream_t hs = (hipStream_t)stream;
+    const size_t per = (size_t)Ns * (Nx / 2 + 1), ubytes = sizeof(cd) * per * nloops, tbytes = sizeof(double) * nloops;
+    // device buffers: interval anchors (u, T), saved results (u, T), J, extrapolation factors
+    char* buf = nullptr;
+    const size_t need = 2 * ubytes + 4 * tbytes + 256;
+    if (hipMalloc((void**)&buf, need) != hipSuccess) return LOOP_EHIP;
+    cd* ua = reinterpret_cast<cd*>(buf);
+    cd* ur = reinterpret_cast<cd*>(buf + ubytes);
+    double* Ta = reinterpret_cast<double*>(buf + 2 * ubytes);
+    double* Tr = Ta + nloops;
+    double* dJ = Tr + nloops;
+    double* df = dJ + nloops;
+    cd* u = reinterpret_cast<cd*>(uhat);
+    std::vector<double> J(nloops), Jan(nloops, -1.0), f(nloops, 0.0);
+    std::vector<char> done(nloops, 0);
+    auto fail = [&](int code) {
+        hipFree(buf);
+        return code;
+    };
+    auto cost = [&]() -> int {
+        int c = loop_cost(L, Nx, Ns, nloops, T, uhat, dJ, ws, ws_bytes, stream);
+        if (c) return c;
+        if (hipMemcpyAsync(J.data(), dJ, tbytes, hipMemcpyDeviceToHost, hs) != hipSuccess) return LOOP_EHIP;
+        if (hipStreamSynchronize(hs) != hipSuccess) return LOOP_EHIP;
+        for (int l = 0; l < nloops; ++l)
+            if (!std::isfinite(J[l])) return LOOP_ENONFINITE;
+        return LOOP_OK;
+    };
+    auto copy_loop = [&](cd* dst_u, double* dst_T, const cd* src_u, const double* src_T, int l) -> bool {
+        return hipMemcpyAsync(dst_u + per * l, src_u + per * l, sizeof(cd) * per, hipMemcpyDeviceToDevice, hs) ==
+                   hipSuccess &&
+               hipMemcpyAsync(dst_T + l, src_T + l, sizeof(double), hipMemcpyDeviceToDevice, hs) == hipSuccess;
+    };
+    auto finish = [&](int l, long long n) -> bool {  // loop l converged at step n: keep its state
+        done[l] = 1;
+        steps[l] = n;
+        J_final[l] = J[l];
+        return copy_loop(ur, Tr, u, T, l);
+    };
+    for (int l = 0; l < nloops; ++l) {
+        steps[l] = -1;
+        extrapolations[l] = 0;
+    }
+    // the initial state (loop_step makes it canonical in place, as the steps below would)
+    if ((st = loop_step(L, Nx, Ns, nloops, T, uhat, dtau, scheme, 0, nullptr, ws, ws_bytes, stream))) return fail(st);
+    if ((st = cost())) return fail(st);
+    long long n = 0;
+    int left = nloops;
+    for (int l = 0; l < nloops; ++l)
+        if (J[l] < J_tol) {
+            if (!finish(l, 0)) return fail(LOOP_EHIP);
+            --left;
+        }
+    while (left > 0 && n < max_steps) {
+        if ((st = loop_step(L, Nx, Ns, nloops, T, uhat, dtau, scheme, stride, nullptr, ws, ws_bytes, stream)))
+            return fail(st);
+        n += stride;
+        if ((st = cost())) return fail(st);
+        bool any = false;
+        for (int l = 0; l < nloops; ++l) {
+            f[l] = 0.0;
+            if (done[l]) continue;
+            if (J[l] < J_tol) {
+                if (!finish(l, n)) return fail(LOOP_EHIP);
+                --left;
+                continue;
+            }
+            if (!accelerate) continue;
+            if (Jan[l] < 0.0) {
+                if (std::sqrt(J[l]) <= sqrtJ_first) {
+                    if (!copy_loop(ua, Ta, u, T, l)) return fail(LOOP_EHIP);
+                    Jan[l] = J[l];
+                }
+            } else if (std::sqrt(J[l]) <= 0.5 * std::sqrt(Jan[l])) {
+                const double rho = std::sqrt(J[l] / Jan[l]);
+                f[l] = rho / (1.0 - rho);
+                any = true;
+            }
+        }
+        if (!any) continue;
+        if (hipMemcpyAsync(df, f.data(), tbytes, hipMemcpyHostToDevice, hs) != hipSuccess) return fail(LOOP_EHIP);
+        if ((st = loop_extrapolate(Nx, Ns, nloops, T, uhat, Ta, reinterpret_cast<const double*>(ua), df, stream)))
+            return fail(st);
+        if ((st = cost())) return fail(st);
+        for (int l = 0; l < nloops; ++l) {
+            if (f[l] == 0.0) continue;
+            ++extrapolations[l];
+            if (J[l] < J_tol) {
+                if (!finish(l, n)) return fail(LOOP_EHIP);
+                --left;
+            } else {
+                if (!copy_loop(ua, Ta, u, T, l)) return fail(LOOP_EHIP);
+                Jan[l] = J[l];
+            }
+        }
+    }
+    // converged loops return the state at which they converged; the others their last state
+    for (int l = 0; l < nloops; ++l) {
+        if (done[l]) {
+            if (!copy_loop(u, T, ur, Tr, l)) return fail(LOOP_EHIP);
+        } else {
+            J_final[l] = J[l];
+        }
+    }
+    if (hipStreamSynchronize(hs) != hipSuccess) return fail(LOOP_EHIP);
+    hipFree(buf);
+    return LOOP_OK;
 }
 
 int loop_set_resident(int mode) {

@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import loopgen  # noqa: E402
+from oracle import accelerate as A  # noqa: E402
 from oracle import ks_loop as K  # noqa: E402
 
 
@@ -64,6 +65,14 @@ def converged(c, dtau, scheme, jtol, chunk):
     }
 
 
+def driven(c, dtau, scheme, jtol, stride, accelerate):
+    """The convergence driver of App. C (oracle/accelerate.py) from workload c's seed."""
+    spec = loopgen.config_loops(c)[0]
+    u, T, J, steps, ext = A.converge(spec.uhat, spec.T, spec.L, dtau, scheme, jtol, stride, 10 ** 6, accelerate)
+    return {"accelerate": accelerate, "steps": steps, "extrapolations": ext, "T_final": float(T), "J_final": float(J),
+            "abs_uhat_final_band": [[j, k, abs(complex(re, im))] for j, k, re, im in band_list(u, spec.Nx, spec.Ns)]}
+
+
 def main():
     data = trajectory(1, 2000, K.EXPLICIT, 1e-4, [0, 1, 10, 100, 1000, 1999])
     with open(os.path.join(HERE, "oracle_traj_plain32x32.json"), "w") as f:
@@ -74,6 +83,12 @@ def main():
         json.dump(data, f, indent=1)
     data = converged(1, 0.05, K.IMEX, 1e-10, 2000)
     with open(os.path.join(HERE, "oracle_converged_plain32x32.json"), "w") as f:
+        json.dump(data, f, indent=1)
+    spec = loopgen.config_loops(1)[0]
+    data = {"workload": loopgen.CONFIGS[1]["name"], "seed": spec.seed, "L": spec.L, "Nx": spec.Nx, "Ns": spec.Ns,
+            "T0": spec.T, "dtau": 0.05, "scheme": "imex", "J_tol": 1e-10, "stride": 100, "sqrtJ_first": 1e-3,
+            "runs": [driven(1, 0.05, K.IMEX, 1e-10, 100, False), driven(1, 0.05, K.IMEX, 1e-10, 100, True)]}
+    with open(os.path.join(HERE, "oracle_accelerated_plain32x32.json"), "w") as f:
         json.dump(data, f, indent=1)
 
 
