@@ -11,6 +11,8 @@ Workloads:
   batched-256x1024    64 loops of 256 x 1024, L = 100, IMEX
   autograd-256x1024   the same 64 loops, G from the autograd path (LoopCost forward and its
                       adjoint backward) and the update by loop_update
+  converge-32x32      the 32 x 32 loop driven to J < 1e-10 (IMEX, dtau = 0.05, J examined every
+                      100 steps), with and without the extrapolations of App. C
   plain-64x128        one 64 x 128 loop, L = 22, IMEX
   plain-32x32         one 32 x 32 loop, L = 22, explicit Euler
 
@@ -40,6 +42,7 @@ WORKLOADS = {
     "autograd-256x1024": 5,
     "plain-64x128": 2,
     "plain-32x32": 1,
+    "converge-32x32": 1,
 }
 
 
@@ -123,6 +126,8 @@ def main():
     api.init()
     dev = "cuda:0"
     stream = torch.cuda.current_stream()
+    if args.workload.startswith("converge"):
+        return bench_converge(args, specs[0])
     if nl == 1 and api.step_form(specs[0].Nx, specs[0].Ns, 1) == "resident":
         return bench_resident(args, cfg, specs[0], steps, dtau, scheme)
     if args.workload.startswith("autograd"):
@@ -387,6 +392,44 @@ def bench_autograd(args, cfg, specs, steps, dtau, scheme):
                      "bytes_per_step": by},
         "cpu_baseline": None,
         "J_mean_end": float(J.mean()),
+    }
+    print(json.dumps(out))
+
+
+def bench_converge(args, spec, dtau=0.05, J_tol=1e-10, stride=100):
+    """The convergence driver (loop_converge) from the loop's seed to J < J_tol, plain and with
+    the extrapolations of App. C. `value` is space-time points advanced per second of the
+    accelerated run, driver included; the steps saved are reported beside it."""
+    import torch
+
+    from paper_2007_06427_amd import api
+    dev = "cuda:0"
+    runs = {}
+    for acc in (False, True):
+        u = torch.from_numpy(spec.uhat[None]).to(dev)
+        T = torch.tensor([spec.T], dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = api.loop_converge(u, T, spec.L, dtau, api.IMEX, J_tol, stride=stride, accelerate=acc)
+        torch.cuda.synchronize()
+        runs[acc] = (r, time.perf_counter() - t0, T.item())
+        assert r["steps"][0] > 0, "did not converge"
+    (rp, wp, Tp), (ra, wa, Ta) = runs[False], runs[True]
+    pts = spec.Nx * spec.Ns
+    out = {
+        "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
+        "value": pts * ra["steps"][0] / wa, "unit": "pts/s", "n_gpus": 1, "steps": ra["steps"][0], "warmup": 0,
+        "ms_per_step": wa / ra["steps"][0] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "loops": 1, "shapes": [[spec.Nx, spec.Ns]], "scheme": "imex",
+                   "dtau": dtau, "J_tol": J_tol, "stride": stride, "form": api.step_form(spec.Nx, spec.Ns, 1),
+                   "parallelism": "none (1 GPU)"},
+        "roofline": None, "cpu_baseline": None,
+        "converge": {"plain_steps": rp["steps"][0], "plain_s": round(wp, 3), "accelerated_steps": ra["steps"][0],
+                     "accelerated_s": round(wa, 3), "extrapolations": ra["extrapolations"][0],
+                     "steps_saved": round(1.0 - ra["steps"][0] / rp["steps"][0], 4),
+                     "time_saved": round(1.0 - wa / wp, 4), "J_final": [rp["J"][0], ra["J"][0]],
+                     "T_final": [Tp, Ta]},
     }
     print(json.dumps(out))
 
