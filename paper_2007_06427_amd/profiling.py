@@ -73,18 +73,21 @@ def summarize_traffic(fetch_csv: str, write_csv: str, workload: str, command: st
     wcopy = max((max(v) for k, v in wcopies), default=None)
     ffac = (fcopy / want_kib) if fcopy else 1.0
     wfac = (wcopy / want_kib) if wcopy else 1.0
+    # Per kernel, the launch over every loop of the plan (the largest grid), taken from
+    # dispatches of the same grid in both runs: a schedule that splits the loops into groups
+    # also launches the kernel on part of them, and the two runs may tune differently.
     kernels = {}
-    for key in sorted(set(fetch) | set(write)):
+    for key in sorted(set(fetch) & set(write), key=lambda k: (k[0], -int(k[1]))):
         name = key[0]
         if not name.startswith("k_rag") and name != "k_batch":
             continue
-        f = sum(fetch.get(key, [0.0])) / max(len(fetch.get(key, [])), 1)
-        w = sum(write.get(key, [0.0])) / max(len(write.get(key, [])), 1)
+        if name in kernels:
+            continue
+        f = sum(fetch[key]) / len(fetch[key])
+        w = sum(write[key]) / len(write[key])
         b = (f / ffac + w / wfac) * 1024
-        prev = kernels.get(name)
-        if prev is None or prev["dispatches"] < len(fetch.get(key, [])):
-            kernels[name] = {"fetch_kib": round(f, 1), "write_kib": round(w, 1), "bytes_per_launch": round(b),
-                             "dispatches": len(fetch.get(key, []))}
+        kernels[name] = {"grid": int(key[1]), "fetch_kib": round(f, 1), "write_kib": round(w, 1),
+                         "bytes_per_launch": round(b), "dispatches": min(len(fetch[key]), len(write[key]))}
     out = {"workload": workload, "command": command, "source_digest": source_digest(),
            "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": fcopy, "write_kib": wcopy,
                                 "fetch_factor": ffac, "write_factor": wfac},
@@ -96,9 +99,12 @@ def summarize_traffic(fetch_csv: str, write_csv: str, workload: str, command: st
              f"Calibration: a {COPY_BYTES >> 20} MiB device copy read FETCH_SIZE {fcopy} KiB and WRITE_SIZE {wcopy} KiB "
              f"(factors {ffac:.3f}, {wfac:.3f}); kernel readings are divided by these.", "",
              f"Kernel source digest: `{source_digest()}`", "",
-             "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | calibrated bytes / launch |", "|---|---:|---:|---:|"]
+             "Per kernel: the launches over every loop (largest grid) found in both runs.", "",
+             "| kernel | grid (work-items) | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | calibrated bytes / launch |",
+             "|---|---:|---:|---:|---:|---:|"]
     for k, v in kernels.items():
-        lines.append(f"| `{k}` | {v['fetch_kib']} | {v['write_kib']} | {v['bytes_per_launch']} |")
+        lines.append(f"| `{k}` | {v['grid']} | {v['dispatches']} | {v['fetch_kib']} | {v['write_kib']} | "
+                     f"{v['bytes_per_launch']} |")
     open(os.path.join(ROOT, "profiles", f"traffic_{workload}.md"), "w").write("\n".join(lines) + "\n")
 
 
