@@ -13,6 +13,9 @@ Workloads:
                       adjoint backward) and the update by loop_update
   converge-32x32      the 32 x 32 loop driven to J < 1e-10 (IMEX, dtau = 0.05, J examined every
                       100 steps), with and without the extrapolations of App. C
+  xi-256x1024         the same 64 loops projected onto centre-symmetric loops (u odd in x),
+                      stepped by loop_step_xi (half the state), with loop_step on the same loops
+                      beside it
   plain-64x128        one 64 x 128 loop, L = 22, IMEX
   plain-32x32         one 32 x 32 loop, L = 22, explicit Euler
 
@@ -40,6 +43,7 @@ WORKLOADS = {
     "batched-ragged-256": 4,
     "batched-256x1024": 5,
     "autograd-256x1024": 5,
+    "xi-256x1024": 5,
     "plain-64x128": 2,
     "plain-32x32": 1,
     "converge-32x32": 1,
@@ -132,6 +136,8 @@ def main():
         return bench_resident(args, cfg, specs[0], steps, dtau, scheme)
     if args.workload.startswith("autograd"):
         return bench_autograd(args, cfg, specs, steps, dtau, scheme)
+    if args.workload.startswith("xi"):
+        return bench_xi(args, cfg, specs, steps, dtau, scheme)
     batch = api.Batch([(s.L, s.Nx, s.Ns) for s in specs])
     pool0 = batch.pack([torch.from_numpy(s.uhat) for s in specs])
     T0 = torch.tensor([s.T for s in specs], dtype=torch.float64, device=dev)
@@ -392,6 +398,83 @@ def bench_autograd(args, cfg, specs, steps, dtau, scheme):
                      "bytes_per_step": by},
         "cpu_baseline": None,
         "J_mean_end": float(J.mean()),
+    }
+    print(json.dumps(out))
+
+
+def xi_step_bytes(Nx, Ns):
+    """Algorithmic HBM bytes of one centre-symmetric step of one loop: W' = Kx Ns real values
+    of one intermediate (8 B), S' = Kx (Ks + 1) complex band values (16 B). B: 2W'; C: 2W' +
+    2S'; D: 3W'; E: 2W' + 2S' (reads and writes as in the full step). 8 (9W' + 8S') bytes."""
+    Kx, Ks = (Nx - 1) // 3, (Ns - 1) // 3
+    W, S = Kx * Ns, Kx * (Ks + 1)
+    return 8 * (9 * W + 8 * S)
+
+
+def bench_xi(args, cfg, specs, steps, dtau, scheme):
+    """Centre-symmetric loops through loop_step_xi: the loops of the workload projected onto
+    u(-x, s) = -u(x, s), K steps in one call (the conversion in and out of the half state is
+    inside the timed region). loop_step on the same projected loops is timed beside it."""
+    import numpy as np
+    import torch
+
+    from paper_2007_06427_amd import api
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream()
+    L = specs[0].L
+    Nx, Ns = specs[0].Nx, specs[0].Ns
+    nl = len(specs)
+    assert all((s.L, s.Nx, s.Ns) == (L, Nx, Ns) for s in specs)
+    ws = api.Workspace(api.xi_workspace_bytes(Nx, Ns, nl))
+    u0 = torch.from_numpy(np.stack([s.uhat for s in specs])).to(dev)
+    T0 = torch.tensor([s.T for s in specs], dtype=torch.float64, device=dev)
+    api.loop_step_xi(u0, T0, L, dtau, scheme, 0, ws=ws)  # zero steps: the projection alone
+
+    def timed(fn, k):
+        u, T = u0.clone(), T0.clone()
+        fn(u, T, args.warmup)
+        torch.cuda.synchronize()
+        u, T = u0.clone(), T0.clone()
+        Jh = torch.zeros(k, nl, dtype=torch.float64, device=dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        fn(u, T, k, Jh)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, e0.elapsed_time(e1) * 1e-3, Jh.cpu().numpy(), u
+
+    wall, gpu_s, J, u = timed(lambda u, T, k, Jh=None: api.loop_step_xi(u, T, L, dtau, scheme, k, J_hist=Jh, ws=ws),
+                              steps)
+    assert ws.status() == 0 and np.all(np.isfinite(J)), "device flagged a non-finite state"
+    wsf = api.Workspace(api.workspace_bytes(Nx, Ns, nl))
+    wall_f, gpu_f, J_f, u_f = timed(lambda u, T, k, Jh=None: api.loop_step(u, T, L, dtau, scheme, k, J_hist=Jh,
+                                                                           ws=wsf), steps)
+    pts = Nx * Ns * nl
+    by = xi_step_bytes(Nx, Ns) * nl
+    achieved = by * steps / gpu_s / 1e9
+    # a plain device copy of known size (counter calibration, as in the batched workloads)
+    src = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
+    torch.empty_like(src).copy_(src)
+    torch.cuda.synchronize()
+    out = {
+        "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
+        "value": pts * steps / wall, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "loops": nl, "shapes": [[Nx, Ns]], "scheme": cfg["scheme"],
+                   "dtau": dtau, "form": "centre-symmetric (loop_step_xi)", "parallelism": "none (1 GPU)"},
+        "gpu_ms_per_step": gpu_s / steps * 1e3,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "whole centre-symmetric step (passes B-E, conversions in and out)",
+                     "bytes_per_step": by},
+        "cpu_baseline": None,
+        "full_path": {"value": pts * steps / wall_f, "unit": "pts/s", "gpu_ms_per_step": gpu_f / steps * 1e3,
+                      "method": "loop_step on the same centre-symmetric loops"},
+        "xi_vs_full": wall_f / wall,
+        "J_rel_diff_vs_full": float(np.max(np.abs(J - J_f) / J_f)),
     }
     print(json.dumps(out))
 

@@ -108,6 +108,23 @@ int loop_cost_grad(double L, int Nx, int Ns, int nloops, const double* T, const 
 int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau,
               int scheme, int nsteps, double* J_hist, void* ws, size_t ws_bytes, void* stream);
 
+/* Centre-symmetric loops (Sec. 3, eq. KS_loop_sym). A loop invariant under
+ * Xi: (x, s) -> (-x, s), u -> -u (u odd in x at every s) stays invariant under the flow, and
+ * every field of the step then has a fixed parity in x: odd fields have purely imaginary,
+ * even ones real x-spectra, column j = 0 vanishes and each column is the transform of a real
+ * sequence in s. loop_step_xi takes nsteps steps storing one real number per (j, s) and the
+ * k >= 0 half of the band, so state and step traffic halve, and each column transform
+ * carries two columns. Input and output use loop_step's rfft layout; the input is first
+ * projected orthogonally onto centre-symmetric loops (u_hat_{j,k} -> (u_hat_{j,k} -
+ * conj u_hat_{j,-k}) / 2, column 0 and everything outside the band -> 0), so for an invariant
+ * loop the results are loop_step's to rounding, and the output is invariant exactly.
+ * Nx <= 512 (LOOP_ENOTSUP otherwise). Work space: loop_step_xi_workspace_bytes (about half of
+ * loop_workspace_bytes; a loop_workspace_bytes work space also serves), prepared by
+ * loop_workspace_init. Other errors, T and J_hist as loop_step; nsteps = 0 only projects. */
+int loop_step_xi_workspace_bytes(int Nx, int Ns, int nloops, size_t* bytes);
+int loop_step_xi(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau, int scheme,
+                 int nsteps, double* J_hist, void* ws, size_t ws_bytes, void* stream);
+
 /* Linear extrapolation of whole loops along their trajectory (App. C), in place:
  *   uhat <- uhat + factor[l] (uhat - uhat_a), T[l] <- T[l] + factor[l] (T[l] - T_a[l]),
  * for nloops loops in the rfft layout; factor (device, nloops) = 0 leaves a loop unchanged.

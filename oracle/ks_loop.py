@@ -188,6 +188,19 @@ def adjoint_grad(uhat: np.ndarray, T: float, L: float):
     return project(G), dT, J
 
 
+def xi_project(uhat: np.ndarray) -> np.ndarray:
+    """Orthogonal projection onto centre-symmetric loops (Sec. 3, eq. KS_loop_sym): the part of
+    u invariant under Xi: u(x, s) -> -u(-x, s), i.e. (u + Xi u) / 2, which in Fourier space is
+    u_hat_{j,k} -> (u_hat_{j,k} - conj u_hat_{j,-k}) / 2 (column 0 and the Nyquist column, for
+    which u_hat_{-j} is the column itself, become 0)."""
+    u = canonical(uhat)
+    Nx, Ns = _shape(u)
+    k_neg = (-np.arange(Ns)) % Ns
+    p = 0.5 * (u - np.conj(u[k_neg, :]))
+    p[:, 0] = 0.0
+    return project(p)
+
+
 def step(uhat: np.ndarray, T: float, L: float, dtau: float, scheme: int = EXPLICIT,
          nsteps: int = 1):
     """Advance the loop by ``nsteps`` fictitious-time steps (Sec. 4.2).

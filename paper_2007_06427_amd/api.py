@@ -214,6 +214,29 @@ def resident_supported(Nx: int, Ns: int) -> bool:
     return bool(_lib.lib().loop_resident_supported(int(Nx), int(Ns)))
 
 
+def loop_step_xi(uhat: torch.Tensor, T: torch.Tensor, L: float, dtau: float, scheme: int = EXPLICIT,
+                 nsteps: int = 1, J_hist: torch.Tensor = None, ws: Workspace = None):
+    """loop_step for centre-symmetric loops (u odd in x), in place, with half the state and
+    traffic. The input is projected onto centre-symmetric loops first."""
+    nl, Nx, Ns = shape_of(uhat)
+    T = _periods(T, nl, uhat.device)
+    if J_hist is not None and (J_hist.dtype != torch.float64 or J_hist.numel() < nsteps * nl
+                               or not J_hist.is_contiguous()):
+        raise ValueError("J_hist must be a contiguous float64 tensor with nsteps * nloops entries")
+    ws = ws or workspace(Nx, Ns, nl)
+    jh = _ptr(J_hist) if J_hist is not None else None
+    check(_lib.lib().loop_step_xi(float(L), Nx, Ns, nl, _ptr(T), _ptr(uhat), float(dtau), int(scheme), int(nsteps),
+                                  jh, ws.ptr, ws.nbytes, _stream_ptr()), "loop_step_xi")
+    return uhat, T
+
+
+def xi_workspace_bytes(Nx: int, Ns: int, nloops: int = 1) -> int:
+    b = ctypes.c_size_t(0)
+    check(_lib.lib().loop_step_xi_workspace_bytes(int(Nx), int(Ns), int(nloops), ctypes.byref(b)),
+          "loop_step_xi_workspace_bytes")
+    return int(b.value)
+
+
 def loop_update(uhat: torch.Tensor, T: torch.Tensor, L: float, Ghat: torch.Tensor, dJdT: torch.Tensor,
                 dtau: float, scheme: int = EXPLICIT):
     nl, Nx, Ns = shape_of(uhat)

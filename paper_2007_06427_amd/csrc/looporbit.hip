@@ -16,6 +16,7 @@
 #include "looporbit.h"
 #include "passes.hpp"
 #include "resident.hpp"
+#include "xi.hpp"
 
 using namespace lo;
 
@@ -60,6 +61,80 @@ __global__ __launch_bounds__(kBlock) void k_colE(Shape sh, Work w, int mode, dou
 // one wavefront per loop
 __global__ __launch_bounds__(64) void k_finalize(Shape sh, Work w, double* T, double* Jout, double* dJdTout) {
     finalize_loop(sh, blockIdx.x, w, T, MODE_COST, 0.0, nullptr, Jout, dJdTout);
+}
+
+// Centre-symmetric form (xi.hpp): one pass per kernel over all loops of one shape.
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_xi_colA(Shape sh, XiWork w, const cd* __restrict__ tw) {
+    __shared__ cd ex[ColG<N>::LDS];
+    xi_col_pass_A<N>(sh, blockIdx.x, w, ex, tw);
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_xi_rowB(Shape sh, XiWork w, const cd* __restrict__ tw) {
+    __shared__ cd lds[RowG<M>::LDS];
+    xi_row_pass_B<M>(sh, blockIdx.x, w, lds, tw);
+}
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_xi_colC(Shape sh, const double* __restrict__ T, XiWork w, double dtau,
+                                                    int scheme, const cd* __restrict__ tw) {
+    __shared__ cd ex[ColG<N>::LDS];
+    __shared__ double red[2 * kBlock / 64];
+    xi_col_pass_C<N>(sh, blockIdx.x, T, w, dtau, scheme, ex, red, tw);
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_xi_rowD(Shape sh, XiWork w, double* T, double dtau, double* J_hist,
+                                                    const cd* __restrict__ tw) {
+    __shared__ cd lds[RowG<M>::LDS];
+    xi_row_pass_D<M>(sh, blockIdx.x, w, T, dtau, J_hist, lds, tw);
+}
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_xi_colE(Shape sh, XiWork w, double dtau, int scheme, int fuseA,
+                                                    const cd* __restrict__ tw) {
+    __shared__ cd ex[ColG<N>::LDS];
+    xi_col_pass_E<N>(sh, blockIdx.x, w, dtau, scheme, fuseA != 0, ex, tw);
+}
+
+// rfft layout -> centre-symmetric band state, projecting orthogonally onto centre-symmetric
+// loops: u_hat_{j,k} -> (u_hat_{j,k} - conj u_hat_{j,-k}) / 2, stored as b = -i u_hat (k >= 0).
+__global__ __launch_bounds__(256) void k_to_xi(Shape sh, const cd* __restrict__ uhat, cd* __restrict__ U) {
+    const int K1 = sh.Ks + 1;
+    const size_t total = (size_t)sh.nloops * sh.Kx * K1;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % K1);
+        const size_t lj = i / K1;
+        const int j = (int)(lj % sh.Kx) + 1;
+        const size_t l = lj / sh.Kx;
+        const cd* u = uhat + l * sh.N * sh.H;
+        const cd a = u[(size_t)k * sh.H + j];
+        const cd b = u[(size_t)((sh.N - k) & (sh.N - 1)) * sh.H + j];
+        const cd d = cd{a.x - b.x, a.y + b.y};  // u_{j,k} - conj u_{j,-k}
+        U[i] = cd{0.5 * d.y, -0.5 * d.x};
+    }
+}
+
+// centre-symmetric band state -> rfft layout, every entry written (0 outside the band):
+// u_hat_{j,k} = i b_{j,k}, u_hat_{j,-k} = i conj b_{j,k}.
+__global__ __launch_bounds__(256) void k_from_xi(Shape sh, const cd* __restrict__ U, cd* __restrict__ out) {
+    const int K1 = sh.Ks + 1;
+    const size_t total = (size_t)sh.nloops * sh.N * sh.H;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(i % sh.H);
+        const size_t le = i / sh.H;
+        const int e = (int)(le % sh.N);
+        const size_t l = le / sh.N;
+        cd v{0.0, 0.0};
+        if (j >= 1 && j <= sh.Kx) {
+            const cd* b = U + (l * sh.Kx + (j - 1)) * K1;
+            if (e <= sh.Ks) {
+                const cd x = b[e];
+                v = cd{-x.y, x.x};
+            } else if (e >= sh.N - sh.Ks) {
+                const cd x = b[sh.N - e];
+                v = cd{x.y, x.x};
+            }
+        }
+        out[i] = v;
+    }
 }
 
 // rfft layout -> band layout U[l][j][kk], column 0 through its Hermitian part (32 x 32 tiles).
@@ -867,6 +942,48 @@ void launch_from_band(const Shape& s, const cd* src, cd* out, hipStream_t st) {
     hipLaunchKernelGGL(k_from_band, grid, dim3(256), 0, st, s, src, out);
 }
 
+// ---------------------------------------------------------------------------- centre-symmetric form
+size_t xi_layout(const Shape& s, char* base, XiWork* w) {
+    size_t off = round_up(sizeof(WsHeader));
+    const size_t band = (size_t)s.nloops * s.Kx * (s.Ks + 1) * sizeof(cd);
+    const size_t inter = (size_t)s.nloops * s.Kx * s.N * sizeof(double);
+    const size_t part = (size_t)s.nloops * s.Kx * 2 * sizeof(double);
+    const size_t scal = (size_t)s.nloops * sizeof(double);
+    XiWork ww{};
+    ww.status = reinterpret_cast<int*>(base);
+    ww.U = reinterpret_cast<cd*>(base + off); off = round_up(off + band);
+    ww.G = reinterpret_cast<cd*>(base + off); off = round_up(off + band);
+    ww.A = reinterpret_cast<double*>(base + off); off = round_up(off + inter);
+    ww.BD = reinterpret_cast<double*>(base + off); off = round_up(off + inter);
+    ww.Cb = reinterpret_cast<double*>(base + off); off = round_up(off + inter);
+    ww.partial = reinterpret_cast<double*>(base + off); off = round_up(off + part);
+    ww.J = reinterpret_cast<double*>(base + off); off = round_up(off + scal);
+    ww.dJdT = reinterpret_cast<double*>(base + off); off = round_up(off + scal);
+    ww.Told = reinterpret_cast<double*>(base + off); off = round_up(off + scal);
+    if (w) *w = ww;
+    return off;
+}
+
+unsigned xi_col_blocks(const Shape& s) {
+    const int F = 8 * kBlock / s.N;  // column pairs per block
+    return (unsigned)(((size_t)s.nloops * ((s.Kx + 1) / 2) + F - 1) / F);
+}
+
+int launch_xi_step(const Shape& s, const XiWork& w, double* T, double dtau, int scheme, int nsteps, double* J_hist,
+                   const cd* tw, hipStream_t hs) {
+    const dim3 cb(xi_col_blocks(s)), rb(row_blocks(s)), th(kBlock);
+    if (nsteps > 0) LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_xi_colA<S_>, cb, th, 0, hs, s, w, tw));
+    for (int i = 0; i < nsteps; ++i) {
+        double* jh = J_hist ? J_hist + (size_t)i * s.nloops : nullptr;
+        LO_SWITCH_SIZE(s.M, hipLaunchKernelGGL(k_xi_rowB<S_>, rb, th, 0, hs, s, w, tw));
+        LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_xi_colC<S_>, cb, th, 0, hs, s, T, w, dtau, scheme, tw));
+        LO_SWITCH_SIZE(s.M, hipLaunchKernelGGL(k_xi_rowD<S_>, rb, th, 0, hs, s, w, T, dtau, jh, tw));
+        LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_xi_colE<S_>, cb, th, 0, hs, s, w, dtau, scheme, i + 1 < nsteps ? 1 : 0,
+                                               tw));
+    }
+    return LOOP_OK;
+}
+
 // ---------------------------------------------------------------------------- resident form
 int last_error() { return hipGetLastError() == hipSuccess ? LOOP_OK : LOOP_EHIP; }
 
@@ -1340,6 +1457,36 @@ int loop_converge(double L, int Nx, int Ns, int nloops, double* T, double* uhat,
     if (hipStreamSynchronize(hs) != hipSuccess) return fail(LOOP_EHIP);
     hipFree(buf);
     return LOOP_OK;
+}
+
+int loop_step_xi_workspace_bytes(int Nx, int Ns, int nloops, size_t* bytes) {
+    int st = check_shape(22.0, Nx, Ns, nloops);
+    if (st) return st;
+    if (!bytes) return LOOP_EINVAL;
+    *bytes = xi_layout(make_shape(22.0, Nx, Ns, nloops), nullptr, nullptr);
+    return LOOP_OK;
+}
+
+int loop_step_xi(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau, int scheme, int nsteps,
+                 double* J_hist, void* ws, size_t ws_bytes, void* stream) {
+    int st = check_shape(L, Nx, Ns, nloops);
+    if (st) return st;
+    if (Nx > 512) return LOOP_ENOTSUP;  // row tiles of the real intermediates, as the batched form
+    if (!aligned(T, 8) || !aligned(uhat, 16) || (J_hist && !aligned(J_hist, 8)) || !aligned(ws, 256))
+        return LOOP_EINVAL;
+    if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1) || nsteps < 0) return LOOP_EINVAL;
+    const Shape s = make_shape(L, Nx, Ns, nloops);
+    if (xi_layout(s, nullptr, nullptr) > ws_bytes) return LOOP_EWORKSPACE;
+    XiWork w;
+    xi_layout(s, static_cast<char*>(ws), &w);
+    const cd* tw;
+    if ((st = get_table(&tw))) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    cd* u = reinterpret_cast<cd*>(uhat);
+    hipLaunchKernelGGL(k_to_xi, dim3(elem_blocks((size_t)nloops * s.Kx * (s.Ks + 1))), dim3(256), 0, hs, s, u, w.U);
+    if ((st = launch_xi_step(s, w, T, dtau, scheme, nsteps, J_hist, tw, hs))) return st;
+    hipLaunchKernelGGL(k_from_xi, dim3(elem_blocks((size_t)nloops * s.N * s.H)), dim3(256), 0, hs, s, w.U, u);
+    return last_error();
 }
 
 int loop_set_resident(int mode) {

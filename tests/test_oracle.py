@@ -352,3 +352,22 @@ def test_autograd_grad_matches_torch_autograd():
     assert abs(J.item() - K.cost(u0, T, L)) < 1e-13 * J.item()
     assert np.max(np.abs(ut.grad.numpy() - g_u)) < 1e-12 * np.max(np.abs(g_u))
     assert abs(Tt.grad.item() - g_T) < 1e-12 * max(abs(g_T), 1e-3 * J.item())
+
+
+def test_xi_project_is_the_orthogonal_projection_onto_invariant_loops():
+    """xi_project (the invariant part (u + Xi u) / 2) is idempotent, lands in the invariant
+    loops, fixes them, is orthogonal in the inner product of eq. inner_product_definition,
+    and identifies u with Xi u."""
+    rng = np.random.default_rng(17)
+    L = 22.0
+    for (Nx, Ns) in [(16, 16), (32, 64), (64, 32)]:
+        u = loopgen.random_band_field(rng, Nx, Ns)
+        P = K.xi_project(u)
+        assert rel(K.xi_project(P), P) < 1e-15
+        assert rel(xi(P), P) < 1e-15
+        v = loopgen.random_xi_symmetric_field(rng, Nx, Ns)
+        assert rel(K.xi_project(v), v) < 1e-15
+        assert abs(K.inner(u - P, P, L)) < 1e-13 * K.inner(u, u, L)
+        assert abs(K.inner(u - P, v, L)) < 1e-13 * np.sqrt(K.inner(u, u, L) * K.inner(v, v, L))
+        assert rel(K.xi_project(xi(u)), P) < 1e-15
+        assert np.all(P[:, 0] == 0)
