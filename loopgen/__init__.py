@@ -43,6 +43,7 @@ __all__ = [
     "random_band_field",
     "random_xi_symmetric_field",
     "from_modes",
+    "random_ks_state",
 ]
 
 
@@ -185,6 +186,23 @@ def random_xi_symmetric_field(rng: np.random.Generator, Nx: int, Ns: int,
                 uhat[k % Ns, j] = v
                 uhat[(-k) % Ns, j] = -np.conj(v)
     return uhat
+
+
+def random_ks_state(rng: np.random.Generator, Nx: int, jmax: int | None = None, scale: float = 1.0,
+                    odd: bool = False) -> np.ndarray:
+    """Random instantaneous KS field (one time) in the rfft layout (Nx//2 + 1,), zero mean, modes
+    1 <= j <= jmax (default the two-thirds band) drawn as scale (xi + i eta) / sqrt(2) in order
+    of j. With odd=True the field is odd in x (centre-symmetric, eq. KS_sym): each mode is
+    i * scale * xi, purely imaginary."""
+    jmax = (Nx - 1) // 3 if jmax is None else jmax
+    u = np.zeros(Nx // 2 + 1, dtype=np.complex128)
+    for j in range(1, jmax + 1):
+        if odd:
+            u[j] = 1j * scale * rng.standard_normal()
+        else:
+            xi, eta = rng.standard_normal(2)
+            u[j] = scale * complex(xi, eta) / np.sqrt(2.0)
+    return u
 
 
 def from_modes(Nx: int, Ns: int, modes: Sequence[tuple]) -> np.ndarray:
