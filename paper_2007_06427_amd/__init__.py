@@ -12,7 +12,7 @@ __all__ = ["EXPLICIT", "IMEX", "LoopOrbitError", "status_string"]
 
 def __getattr__(name):
     # the tensor-level API needs torch; import it lazily so that the ctypes layer loads without it
-    if name in ("api", "autograd"):
+    if name in ("api", "autograd", "initial_loops"):
         import importlib
         return importlib.import_module(f".{name}", __name__)
     raise AttributeError(name)

@@ -21,7 +21,7 @@ LOOP_EHANG = -6
 EXPLICIT = 0
 IMEX = 1
 
-# every symbol include/looporbit.h declares
+# every symbol include/looporbit.h and include/ks_initial_loops.h declare
 EXPORTS = [
     "loop_init", "loop_shutdown", "loop_workspace_bytes", "loop_workspace_init", "loop_residual",
     "loop_cost", "loop_adjoint_grad", "loop_cost_grad", "loop_step", "loop_set_resident",
@@ -31,6 +31,7 @@ EXPORTS = [
     "loop_batch_info", "loop_batch_workspace_init", "loop_batch_step", "loop_batch_load", "loop_batch_pass",
     "loop_batch_store", "loop_batch_set_variant", "loop_batch_get_config", "loop_batch_autotune",
     "loop_status_sync", "loop_status_string",
+    "ks_integrate", "ks_recurrences", "ks_segments_to_loops",
 ]
 
 
@@ -82,6 +83,9 @@ _SIGS = {
     "loop_batch_autotune": ([_p, _p, _p, _i, ctypes.POINTER(_d), _p, _sz, _p], _i),
     "loop_status_sync": ([_p, _p], _i),
     "loop_status_string": ([_i], ctypes.c_char_p),
+    "ks_integrate": ([_d, _i, _i, _i, _d, _i, _i, _p, _p, _p, _i, _p], _i),
+    "ks_recurrences": ([_i, _i, _p, _i, _d, _d, _d, _d, _i, _p, _p, _p], _i),
+    "ks_segments_to_loops": ([_i, _i, _i, _p, _i, _i, _p, _d, _i, _i, _p, _p, _p], _i),
 }
 
 
