@@ -16,6 +16,11 @@ Workloads:
   xi-256x1024         the same 64 loops projected onto centre-symmetric loops (u odd in x),
                       stepped by loop_step_xi (half the state), with loop_step on the same loops
                       beside it
+  orbits-39           the initial-loop pipeline of Sec. 4.3 and the loop dynamics together:
+                      64 centre-symmetric chaotic KS runs at L = 39 (64 modes, ETDRK4), their
+                      norm recurrences with 20 <= T <= 160 made into 64 x 64 loops, and the
+                      loops driven by loop_converge (IMEX, dtau = 0.15, App. C extrapolations);
+                      reports the periods of the orbits found beside the paper's
   plain-64x128        one 64 x 128 loop, L = 22, IMEX
   plain-32x32         one 32 x 32 loop, L = 22, explicit Euler
 
@@ -47,6 +52,7 @@ WORKLOADS = {
     "plain-64x128": 2,
     "plain-32x32": 1,
     "converge-32x32": 1,
+    "orbits-39": 1,
 }
 
 
@@ -132,6 +138,8 @@ def main():
     stream = torch.cuda.current_stream()
     if args.workload.startswith("converge"):
         return bench_converge(args, specs[0])
+    if args.workload.startswith("orbits"):
+        return bench_orbits(args)
     if nl == 1 and api.step_form(specs[0].Nx, specs[0].Ns, 1) == "resident":
         return bench_resident(args, cfg, specs[0], steps, dtau, scheme)
     if args.workload.startswith("autograd"):
@@ -513,6 +521,90 @@ def bench_converge(args, spec, dtau=0.05, J_tol=1e-10, stride=100):
                      "steps_saved": round(1.0 - ra["steps"][0] / rp["steps"][0], 4),
                      "time_saved": round(1.0 - wa / wp, 4), "J_final": [rp["J"][0], ra["J"][0]],
                      "T_final": [Tp, Ta]},
+    }
+    print(json.dumps(out))
+
+
+# periods of the centre-symmetric orbits at L = 39 the paper reports (Sec. 4.4, Fig. 5)
+PAPER_PERIODS = [25.37, 53.13, 76.61, 106.98, 123.37, 147.42]
+
+
+def bench_orbits(args, E=64, per_run=2, chunk=400_000, J_tol=5e-25):
+    """Initial loops from chaotic runs (Sec. 4.3) driven to periodic orbits (Sec. 4.4).
+
+    The runs: E centre-symmetric KS runs at L = 39 on 64 modes (ETDRK4, dt = 0.05), started
+    from seeded small odd fields, 4000 steps of transient and 20000 recorded steps sampled
+    every 2. Pairs of norm maxima within 1% and 20 <= T <= 160 give the loops (the first
+    `per_run` pairs of each run; 64 x 64 grid, temporal modes |k| <= 10). loop_converge then
+    drives all loops together in chunks of `chunk` steps (IMEX, dtau = 0.15, J examined every
+    1000 steps, App. C extrapolations), until J < J_tol (the paper's sqrt(J) < 1e-12 is J < 5e-25
+    in the J = 1/2 int int r^2 used here) or --steps steps. `value` is space-time points of
+    the loop dynamics advanced per second."""
+    import numpy as np
+    import torch
+
+    import loopgen
+    from paper_2007_06427_amd import api, initial_loops as il
+    dev = "cuda:0"
+    L, Nx, dt, every = 39.0, 64, 0.05, 2
+    total = args.steps if args.steps is not None else 2_000_000
+    rng = np.random.default_rng(2020)
+    u0 = torch.from_numpy(np.stack([loopgen.random_ks_state(rng, Nx, scale=0.1, odd=True) for _ in range(E)])).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loops, T, triples, norms, snaps = il.initial_loops(u0, L, dt, 4000, 20000, every, 0.01, 20.0, 160.0, Ns=64, kc=10,
+                                                       per_run=per_run)
+    torch.cuda.synchronize()
+    t_pipe = time.perf_counter() - t0
+    nl = loops.shape[0]
+    T0 = T.cpu().numpy().copy()
+    steps = np.full(nl, -1, dtype=np.int64)
+    done, t_conv, J = 0, 0.0, None
+    while done < total and np.any(steps < 0):
+        k = min(chunk, total - done)
+        t1 = time.perf_counter()
+        r = api.loop_converge(loops, T, L, 0.15, api.IMEX, J_tol, stride=1000, max_steps=k, accelerate=True)
+        torch.cuda.synchronize()
+        t_conv += time.perf_counter() - t1
+        newly = (np.array(r["steps"]) >= 0) & (steps < 0)
+        steps[newly] = done + np.array(r["steps"])[newly]
+        J = np.array(r["J"])
+        done += k
+        print(f"# {done} steps: {int(np.sum(steps >= 0))} of {nl} loops below J_tol, "
+              f"{int(np.sum(J < 5e-21))} with sqrt(J_paper) < 1e-10", file=sys.stderr, flush=True)
+    u = loops.cpu().numpy()
+    Tf = T.cpu().numpy()
+    # equilibria (no s-dependence) converge with T left free; repeats are multiples of a shorter orbit
+    s_energy = np.sum(np.abs(u[:, 1:, :]) ** 2, axis=(1, 2)) / np.maximum(np.sum(np.abs(u) ** 2, axis=(1, 2)), 1e-300)
+    found = []
+    for i in np.argsort(Tf):
+        if J[i] >= 5e-21 or s_energy[i] < 1e-12:
+            continue
+        if any(abs(Tf[i] - f["T"]) < 1e-3 * f["T"] for f in found):
+            next(f for f in found if abs(Tf[i] - f["T"]) < 1e-3 * f["T"])["count"] += 1
+            continue
+        found.append({"T": round(float(Tf[i]), 4), "sqrtJ_paper": float(np.sqrt(2 * J[i])), "count": 1})
+    for f in found:
+        base = [g["T"] for g in found if g["T"] < f["T"] and abs(f["T"] / g["T"] - round(f["T"] / g["T"])) < 1e-3]
+        f["repeat_of"] = base[0] if base else None
+    pts = nl * 64 * 64
+    out = {
+        "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
+        "value": pts * done / t_conv, "unit": "pts/s", "n_gpus": 1, "steps": done, "warmup": 0,
+        "ms_per_step": t_conv / done * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded chaotic KS runs)",
+        "config": {"workload": args.workload, "runs": E, "loops": nl, "shapes": [[64, 64]], "L": L, "scheme": "imex",
+                   "dtau": 0.15, "J_tol": J_tol, "form": api.step_form(64, 64, nl), "parallelism": "none (1 GPU)"},
+        "roofline": None, "cpu_baseline": None,
+        "pipeline": {"seconds": round(t_pipe, 3), "run_steps_per_s": E * 24000 / t_pipe,
+                     "T0_range": [round(float(T0.min()), 2), round(float(T0.max()), 2)]},
+        "orbits": {"converged_below_J_tol": int(np.sum(steps >= 0)),
+                   "sqrtJ_paper_below_1e-10": int(np.sum(J < 5e-21)),
+                   "equilibria": int(np.sum((J < 5e-21) & (s_energy < 1e-12))),
+                   "periods": found,
+                   "paper_periods": PAPER_PERIODS,
+                   "paper_periods_matched": [p for p in PAPER_PERIODS
+                                             if any(abs(f["T"] - p) < 0.01 for f in found)]},
     }
     print(json.dumps(out))
 
