@@ -188,6 +188,53 @@ def adjoint_grad(uhat: np.ndarray, T: float, L: float):
     return project(G), dT, J
 
 
+def expanded_grad(uhat: np.ndarray, T: float, L: float):
+    """The paper's own evaluation of the flow (Sec. 4.2, eq. KS_G_1): G_1 = G_1L + G_1NL with
+        G_1L  = (1/T^2) u_ss - u_xxxxxxxx - 2 u_xxxxxx - u_xxxx = lambda u_hat,
+        G_1NL = -5 u_xxxx u_x - 10 u_xxx u_xx - 3 u_xx u_x + u^2 u_xx + u u_x^2
+                + (2u/T) u_xs + (1/T) u_x u_s,
+    the derivatives formed in spectral space, the fields on the grid, the products pointwise
+    there, and the sum transformed back and truncated to the band. dJ/dT = int int (1/T^2) u_s r
+    and J = 1/2 int int r^2 take their integrands on the grid, with r = -(1/T) u_s - u u_x - u_xx
+    - u_xxxx formed pointwise there (Sec. 4.2). Returns (G1_hat, dJ/dT, J).
+
+    The cubic products are not free of aliasing under the two-thirds rule, and no intermediate
+    is truncated, so this G differs from adjoint_grad's by truncation and aliasing errors; for
+    fields of modes |j| <= Kx/3, |k| <= Ks/3 every product stays in the band and the two agree."""
+    u = canonical(uhat)
+    Nx, Ns = _shape(u)
+    g = to_grid
+    U, Ux, Uxx = g(u), g(d_x(u, L)), g(d_xx(u, L))
+    Uxxx, Uxxxx = g(d_x(d_xx(u, L), L)), g(d_xxxx(u, L))
+    Us, Uxs = g(d_s(u, L)), g(d_x(d_s(u, L), L))
+    nl = (-5.0 * Uxxxx * Ux - 10.0 * Uxxx * Uxx - 3.0 * Uxx * Ux + U * U * Uxx + U * Ux * Ux
+          + (2.0 / T) * U * Uxs + (1.0 / T) * Ux * Us)
+    G = lam(T, L, Nx, Ns) * u + project(from_grid(nl))
+    r = -(1.0 / T) * Us - U * Ux - Uxx - Uxxxx
+    return project(G), space_time_integral(Us * r / (T * T), L), 0.5 * space_time_integral(r * r, L)
+
+
+def step_expanded(uhat: np.ndarray, T: float, L: float, dtau: float, scheme: int = EXPLICIT, nsteps: int = 1):
+    """The paper's step on eq. KS_G_1 (Sec. 4.2): u_hat' = (u_hat + dtau G_1NL) / (1 - dtau lambda)
+    (IMEX) or u_hat + dtau G_1 (explicit), T' = T - dtau dJ/dT, from expanded_grad."""
+    u = canonical(uhat)
+    Nx, Ns = _shape(u)
+    J_hist = np.zeros(nsteps)
+    for i in range(nsteps):
+        G, dT, J = expanded_grad(u, T, L)
+        J_hist[i] = J
+        lm = lam(T, L, Nx, Ns)
+        if scheme == EXPLICIT:
+            u_new = u + dtau * G
+        elif scheme == IMEX:
+            u_new = (u + dtau * (G - lm * u)) / (1.0 - dtau * lm)
+        else:
+            raise ValueError("scheme must be EXPLICIT (0) or IMEX (1)")
+        T = T - dtau * dT
+        u = project(u_new)
+    return u, T, J_hist
+
+
 def xi_project(uhat: np.ndarray) -> np.ndarray:
     """Orthogonal projection onto centre-symmetric loops (Sec. 3, eq. KS_loop_sym): the part of
     u invariant under Xi: u(x, s) -> -u(-x, s), i.e. (u + Xi u) / 2, which in Fourier space is
