@@ -21,6 +21,8 @@ Workloads:
                       norm recurrences with 20 <= T <= 160 made into 64 x 64 loops, and the
                       loops driven by loop_converge (IMEX, dtau = 0.15, App. C extrapolations);
                       reports the periods of the orbits found beside the paper's
+  expanded-256x1024   the 64 loops of 256 x 1024 stepped by the paper's own expanded form of the
+                      flow (eq. KS_G_1, loop_step_expanded), with loop_step beside it
   plain-64x128        one 64 x 128 loop, L = 22, IMEX
   plain-32x32         one 32 x 32 loop, L = 22, explicit Euler
 
@@ -49,6 +51,7 @@ WORKLOADS = {
     "batched-256x1024": 5,
     "autograd-256x1024": 5,
     "xi-256x1024": 5,
+    "expanded-256x1024": 5,
     "plain-64x128": 2,
     "plain-32x32": 1,
     "converge-32x32": 1,
@@ -146,6 +149,8 @@ def main():
         return bench_autograd(args, cfg, specs, steps, dtau, scheme)
     if args.workload.startswith("xi"):
         return bench_xi(args, cfg, specs, steps, dtau, scheme)
+    if args.workload.startswith("expanded"):
+        return bench_expanded(args, cfg, specs, steps, dtau, scheme)
     batch = api.Batch([(s.L, s.Nx, s.Ns) for s in specs])
     pool0 = batch.pack([torch.from_numpy(s.uhat) for s in specs])
     T0 = torch.tensor([s.T for s in specs], dtype=torch.float64, device=dev)
@@ -482,6 +487,74 @@ def bench_xi(args, cfg, specs, steps, dtau, scheme):
         "full_path": {"value": pts * steps / wall_f, "unit": "pts/s", "gpu_ms_per_step": gpu_f / steps * 1e3,
                       "method": "loop_step on the same centre-symmetric loops"},
         "xi_vs_full": wall_f / wall,
+        "J_rel_diff_vs_full": float(np.max(np.abs(J - J_f) / J_f)),
+    }
+    print(json.dumps(out))
+
+
+def expanded_step_bytes(Nx, Ns):
+    """Algorithmic HBM bytes of one expanded-form step of one loop (16 B per complex value, W and
+    S as in pass_bytes): XB reads A and Cb and writes the transformed G_1NL (3W); XC reads it and
+    u_hat and writes u_hat' and the next A and Cb (3W + 2S). 16 (6W + 2S) bytes."""
+    W, S = band(Nx, Ns)
+    return 16 * (6 * W + 2 * S)
+
+
+def bench_expanded(args, cfg, specs, steps, dtau, scheme):
+    """The paper's expanded form (loop_step_expanded) on the workload's loops, K steps in one call,
+    with loop_step on the same loops timed beside it."""
+    import numpy as np
+    import torch
+
+    from paper_2007_06427_amd import api
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream()
+    L = specs[0].L
+    Nx, Ns = specs[0].Nx, specs[0].Ns
+    nl = len(specs)
+    assert all((s.L, s.Nx, s.Ns) == (L, Nx, Ns) for s in specs)
+    ws = api.Workspace(api.workspace_bytes(Nx, Ns, nl))
+    u0 = torch.from_numpy(np.stack([s.uhat for s in specs])).to(dev)
+    T0 = torch.tensor([s.T for s in specs], dtype=torch.float64, device=dev)
+
+    def timed(fn, k):
+        u, T = u0.clone(), T0.clone()
+        fn(u, T, args.warmup)
+        torch.cuda.synchronize()
+        u, T = u0.clone(), T0.clone()
+        Jh = torch.zeros(k, nl, dtype=torch.float64, device=dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        fn(u, T, k, Jh)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, e0.elapsed_time(e1) * 1e-3, Jh.cpu().numpy()
+
+    wall, gpu_s, J = timed(lambda u, T, k, Jh=None: api.loop_step_expanded(u, T, L, dtau, scheme, k, J_hist=Jh, ws=ws),
+                           steps)
+    assert ws.status() == 0 and np.all(np.isfinite(J)), "device flagged a non-finite state"
+    wall_f, gpu_f, J_f = timed(lambda u, T, k, Jh=None: api.loop_step(u, T, L, dtau, scheme, k, J_hist=Jh, ws=ws),
+                               steps)
+    pts = Nx * Ns * nl
+    by = expanded_step_bytes(Nx, Ns) * nl
+    achieved = by * steps / gpu_s / 1e9
+    out = {
+        "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
+        "value": pts * steps / wall, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "loops": nl, "shapes": [[Nx, Ns]], "scheme": cfg["scheme"],
+                   "dtau": dtau, "form": "expanded (eq. KS_G_1, loop_step_expanded)", "parallelism": "none (1 GPU)"},
+        "gpu_ms_per_step": gpu_s / steps * 1e3,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "whole expanded-form step (XB, finalize, XC with the next XA)", "bytes_per_step": by},
+        "cpu_baseline": None,
+        "full_path": {"value": pts * steps / wall_f, "unit": "pts/s", "gpu_ms_per_step": gpu_f / steps * 1e3,
+                      "method": "loop_step on the same loops"},
+        "expanded_vs_full": wall_f / wall,
         "J_rel_diff_vs_full": float(np.max(np.abs(J - J_f) / J_f)),
     }
     print(json.dumps(out))

@@ -125,6 +125,28 @@ int loop_step_xi_workspace_bytes(int Nx, int Ns, int nloops, size_t* bytes);
 int loop_step_xi(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau, int scheme,
                  int nsteps, double* J_hist, void* ws, size_t ws_bytes, void* stream);
 
+/* The paper's own evaluation of the flow (Sec. 4.2, eq. KS_G_1), for cross-checks and for
+ * the paper's step: G_1 = lambda u_hat + P(G_1NL), where
+ *   G_1NL = -5 u_xxxx u_x - 10 u_xxx u_xx - 3 u_xx u_x + u^2 u_xx + u u_x^2 + (2u/T) u_xs
+ *           + (1/T) u_x u_s
+ * is formed pointwise on the Nx x Ns grid from derivatives taken in spectral space, and P
+ * is the transform back with the two-thirds truncation. dJ/dT = int int (1/T^2) u_s r and
+ * J = 1/2 int int r^2 take their integrands on the grid, with r = -(1/T) u_s - u u_x - u_xx -
+ * u_xxxx formed pointwise (the paper's (0, 0)-mode rule).
+ * The cubic products of G_1NL alias under the two-thirds rule and no intermediate is
+ * truncated, so this G differs from loop_adjoint_grad's by aliasing and truncation errors:
+ * the two agree to rounding where every product stays in the band (modes |j| <= Kx/2,
+ * |k| <= Ks/2), dJ/dT agrees on every loop, and J is at least loop_cost's (the grid residual
+ * keeps the out-of-band part of u u_x).
+ * loop_expanded_grad: Ghat (rfft layout, band), dJdT and J (each nloops, NULL to skip), as
+ * loop_adjoint_grad. loop_step_expanded: nsteps steps u_hat' = (u_hat + dtau P(G_1NL)) /
+ * (1 - dtau lambda) (IMEX) or u_hat + dtau G_1 (explicit), T' = T - dtau dJ/dT; J_hist and
+ * errors as loop_step. Nx <= 512 (LOOP_ENOTSUP otherwise). Work space: loop_workspace_bytes. */
+int loop_expanded_grad(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat, double* Ghat,
+                       double* dJdT, double* J, void* ws, size_t ws_bytes, void* stream);
+int loop_step_expanded(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau, int scheme,
+                       int nsteps, double* J_hist, void* ws, size_t ws_bytes, void* stream);
+
 /* Linear extrapolation of whole loops along their trajectory (App. C), in place:
  *   uhat <- uhat + factor[l] (uhat - uhat_a), T[l] <- T[l] + factor[l] (T[l] - T_a[l]),
  * for nloops loops in the rfft layout; factor (device, nloops) = 0 leaves a loop unchanged.

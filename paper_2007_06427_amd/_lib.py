@@ -26,7 +26,7 @@ EXPORTS = [
     "loop_init", "loop_shutdown", "loop_workspace_bytes", "loop_workspace_init", "loop_residual",
     "loop_cost", "loop_adjoint_grad", "loop_cost_grad", "loop_step", "loop_set_resident",
     "loop_resident_supported", "loop_step_form", "loop_extrapolate", "loop_converge", "loop_step_xi",
-    "loop_step_xi_workspace_bytes", "loop_update", "loop_batch_create", "loop_batch_set_schedule", "loop_batch_set_streams",
+    "loop_step_xi_workspace_bytes", "loop_expanded_grad", "loop_step_expanded", "loop_update", "loop_batch_create", "loop_batch_set_schedule", "loop_batch_set_streams",
     "loop_batch_destroy",
     "loop_batch_info", "loop_batch_workspace_init", "loop_batch_step", "loop_batch_load", "loop_batch_pass",
     "loop_batch_store", "loop_batch_set_variant", "loop_batch_get_config", "loop_batch_autotune",
@@ -67,6 +67,8 @@ _SIGS = {
     "loop_extrapolate": ([_i, _i, _i, _p, _p, _p, _p, _p, _p], _i),
     "loop_step_xi": ([_d, _i, _i, _i, _p, _p, _d, _i, _i, _p, _p, _sz, _p], _i),
     "loop_step_xi_workspace_bytes": ([_i, _i, _i, ctypes.POINTER(_sz)], _i),
+    "loop_expanded_grad": ([_d, _i, _i, _i, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
+    "loop_step_expanded": ([_d, _i, _i, _i, _p, _p, _d, _i, _i, _p, _p, _sz, _p], _i),
     "loop_converge": ([_d, _i, _i, _i, _p, _p, _d, _i, _d, _i, ctypes.c_longlong, _i, _d,
                        ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_i), ctypes.POINTER(_d), _p, _sz, _p], _i),
     "loop_batch_set_schedule": ([_p, _i], _i),

@@ -230,6 +230,35 @@ def loop_step_xi(uhat: torch.Tensor, T: torch.Tensor, L: float, dtau: float, sch
     return uhat, T
 
 
+def loop_expanded_grad(uhat: torch.Tensor, T, L: float, ws: Workspace = None):
+    """The paper's expanded form of the flow (eq. KS_G_1): (G1_hat, dJ/dT, J), as
+    loop_adjoint_grad returns them."""
+    nl, Nx, Ns = shape_of(uhat)
+    T = _periods(T, nl, uhat.device)
+    G = torch.empty_like(uhat)
+    dT = torch.empty(nl, dtype=torch.float64, device=uhat.device)
+    J = torch.empty(nl, dtype=torch.float64, device=uhat.device)
+    ws = ws or workspace(Nx, Ns, nl)
+    check(_lib.lib().loop_expanded_grad(float(L), Nx, Ns, nl, _ptr(T), _ptr(uhat), _ptr(G), _ptr(dT), _ptr(J), ws.ptr,
+                                        ws.nbytes, _stream_ptr()), "loop_expanded_grad")
+    return G, dT, J
+
+
+def loop_step_expanded(uhat: torch.Tensor, T: torch.Tensor, L: float, dtau: float, scheme: int = EXPLICIT,
+                       nsteps: int = 1, J_hist: torch.Tensor = None, ws: Workspace = None):
+    """The paper's step on the expanded form (Sec. 4.2), in place, as loop_step."""
+    nl, Nx, Ns = shape_of(uhat)
+    T = _periods(T, nl, uhat.device)
+    if J_hist is not None and (J_hist.dtype != torch.float64 or J_hist.numel() < nsteps * nl
+                               or not J_hist.is_contiguous()):
+        raise ValueError("J_hist must be a contiguous float64 tensor with nsteps * nloops entries")
+    ws = ws or workspace(Nx, Ns, nl)
+    jh = _ptr(J_hist) if J_hist is not None else None
+    check(_lib.lib().loop_step_expanded(float(L), Nx, Ns, nl, _ptr(T), _ptr(uhat), float(dtau), int(scheme),
+                                        int(nsteps), jh, ws.ptr, ws.nbytes, _stream_ptr()), "loop_step_expanded")
+    return uhat, T
+
+
 def xi_workspace_bytes(Nx: int, Ns: int, nloops: int = 1) -> int:
     b = ctypes.c_size_t(0)
     check(_lib.lib().loop_step_xi_workspace_bytes(int(Nx), int(Ns), int(nloops), ctypes.byref(b)),

@@ -17,6 +17,7 @@
 #include "passes.hpp"
 #include "resident.hpp"
 #include "xi.hpp"
+#include "expanded.hpp"
 
 using namespace lo;
 
@@ -61,6 +62,34 @@ __global__ __launch_bounds__(kBlock) void k_colE(Shape sh, Work w, int mode, dou
 // one wavefront per loop
 __global__ __launch_bounds__(64) void k_finalize(Shape sh, Work w, double* T, double* Jout, double* dJdTout) {
     finalize_loop(sh, blockIdx.x, w, T, MODE_COST, 0.0, nullptr, Jout, dJdTout);
+}
+
+// The paper's expanded form of the flow (expanded.hpp): three passes and a per-loop finalize.
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_xA(Shape sh, Work w, const cd* __restrict__ tw) {
+    __shared__ cd ex[ColG<N>::LDS];
+    col_pass_XA<N>(sh, blockIdx.x, w, ex, tw);
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_xB(Shape sh, Work w, const double* __restrict__ T,
+                                               const cd* __restrict__ tw) {
+    extern __shared__ cd lds[];
+    row_pass_X<M>(sh, blockIdx.x, w, T, lds, tw);
+}
+// one wavefront per loop: the row sums (in G) of loop blockIdx.x into J, dJ/dT (and T's update)
+__global__ __launch_bounds__(64) void k_x_finalize(Shape sh, Work w, double* T, int mode, double dtau,
+                                                   double* J_hist, double* Jout, double* dJdTout) {
+    Shape sx = sh;
+    sx.C = sh.N;  // one partial pair per row
+    Work wf = w;
+    wf.partial = reinterpret_cast<double*>(w.G);
+    finalize_loop(sx, blockIdx.x, wf, T, mode, dtau, J_hist, Jout, dJdTout);
+}
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_xC(Shape sh, Work w, const double* __restrict__ Tl, int mode, double dtau,
+                                               int scheme, int fuse, const cd* __restrict__ tw) {
+    __shared__ cd ex[ColG<N>::LDS];
+    col_pass_XC<N>(sh, blockIdx.x, w, Tl, mode, dtau, scheme, fuse != 0, ex, tw);
 }
 
 // Centre-symmetric form (xi.hpp): one pass per kernel over all loops of one shape.
@@ -942,6 +971,44 @@ void launch_from_band(const Shape& s, const cd* src, cd* out, hipStream_t st) {
     hipLaunchKernelGGL(k_from_band, grid, dim3(256), 0, st, s, src, out);
 }
 
+// ---------------------------------------------------------------------------- expanded form
+// The row pass keeps two input tiles and the exchange regions apart in LDS (up to 83 KB),
+// so it takes dynamic LDS; rows of up to 512 points.
+int launch_xB(const Shape& s, const Work& w, const double* T, const cd* tw, hipStream_t st) {
+    int rc = LOOP_ENOTSUP;
+    host_size_switch<8, 512>(s.M, [&](auto c) {
+        constexpr int M = decltype(c)::value;
+        constexpr size_t bytes = XRowG<M>::LDS * sizeof(cd);
+        auto k = k_xB<M>;
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes) != hipSuccess) {
+            rc = LOOP_EHIP;
+            return;
+        }
+        hipLaunchKernelGGL(k, dim3(row_blocks(s)), dim3(kBlock), bytes, st, s, w, T, tw);
+        rc = LOOP_OK;
+    });
+    return rc;
+}
+
+int launch_x_grad_or_step(const Shape& s, const Work& w, double* T, int mode, double dtau, int scheme, int nsteps,
+                          double* J_hist, double* Jout, double* dJdTout, const cd* tw, hipStream_t hs) {
+    const dim3 cb(col_blocks(s)), th(kBlock);
+    int st;
+    LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_xA<S_>, cb, th, 0, hs, s, w, tw));
+    const int n = mode == MODE_STEP ? nsteps : 1;
+    for (int i = 0; i < n; ++i) {
+        if ((st = launch_xB(s, w, T, tw, hs))) return st;
+        double* jh = (mode == MODE_STEP && J_hist) ? J_hist + (size_t)i * s.nloops : nullptr;
+        hipLaunchKernelGGL(k_x_finalize, dim3(s.nloops), dim3(64), 0, hs, s, w, T, mode == MODE_STEP ? MODE_STEP : MODE_COST,
+                           dtau, jh, Jout, dJdTout);
+        const double* Tl = mode == MODE_STEP ? w.Told : T;
+        const int fuse = (mode == MODE_STEP && i + 1 < n) ? 1 : 0;
+        LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_xC<S_>, cb, th, 0, hs, s, w, Tl, mode, dtau, scheme, fuse, tw));
+    }
+    return LOOP_OK;
+}
+
 // ---------------------------------------------------------------------------- centre-symmetric form
 size_t xi_layout(const Shape& s, char* base, XiWork* w) {
     size_t off = round_up(sizeof(WsHeader));
@@ -1325,6 +1392,45 @@ int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, dou
         if ((st = launch_D(s, w, T, MODE_STEP, dtau, jh, nullptr, nullptr, tw, hs))) return st;
         if ((st = launch_E(s, w, MODE_STEP, dtau, scheme, i + 1 < nsteps, tw, hs))) return st;
     }
+    launch_from_band(s, w.U, u, hs);
+    return last_error();
+}
+
+int loop_expanded_grad(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat, double* Ghat,
+                       double* dJdT, double* J, void* ws, size_t ws_bytes, void* stream) {
+    Shape s;
+    Work w;
+    const cd* tw;
+    if (!aligned(T, 8) || !aligned(uhat, 16) || !aligned(Ghat, 16) || (const void*)uhat == (const void*)Ghat)
+        return LOOP_EINVAL;
+    if ((dJdT && !aligned(dJdT, 8)) || (J && !aligned(J, 8))) return LOOP_EINVAL;
+    int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
+    if (st) return st;
+    if (Nx > 512 || (size_t)s.C * s.NB < (size_t)s.N) return LOOP_ENOTSUP;
+    hipStream_t hs = (hipStream_t)stream;
+    launch_to_band(s, reinterpret_cast<const cd*>(uhat), w.U, hs);
+    if ((st = launch_x_grad_or_step(s, w, const_cast<double*>(T), MODE_GRAD, 0.0, 0, 1, nullptr, J, dJdT, tw, hs)))
+        return st;
+    launch_from_band(s, w.G, reinterpret_cast<cd*>(Ghat), hs);
+    return last_error();
+}
+
+int loop_step_expanded(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau, int scheme,
+                       int nsteps, double* J_hist, void* ws, size_t ws_bytes, void* stream) {
+    Shape s;
+    Work w;
+    const cd* tw;
+    if (!aligned(T, 8) || !aligned(uhat, 16) || (J_hist && !aligned(J_hist, 8))) return LOOP_EINVAL;
+    if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1) || nsteps < 0) return LOOP_EINVAL;
+    int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
+    if (st) return st;
+    if (Nx > 512 || (size_t)s.C * s.NB < (size_t)s.N) return LOOP_ENOTSUP;
+    hipStream_t hs = (hipStream_t)stream;
+    cd* u = reinterpret_cast<cd*>(uhat);
+    launch_to_band(s, u, w.U, hs);
+    if (nsteps > 0 &&
+        (st = launch_x_grad_or_step(s, w, T, MODE_STEP, dtau, scheme, nsteps, J_hist, nullptr, nullptr, tw, hs)))
+        return st;
     launch_from_band(s, w.U, u, hs);
     return last_error();
 }
