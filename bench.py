@@ -17,8 +17,8 @@ Workloads:
                       stepped by loop_step_xi (half the state), with loop_step on the same loops
                       beside it
   orbits-39           the initial-loop pipeline of Sec. 4.3 and the loop dynamics together:
-                      64 centre-symmetric chaotic KS runs at L = 39 (64 modes, ETDRK4), their
-                      norm recurrences with 20 <= T <= 160 made into 64 x 64 loops, and the
+                      128 centre-symmetric chaotic KS runs at L = 39 (64 modes, ETDRK4), their
+                      norm recurrences with 20 <= T <= 160 made into 256 loops of 64 x 64, the
                       loops driven by loop_converge (IMEX, dtau = 0.15, App. C extrapolations);
                       reports the periods of the orbits found beside the paper's
   expanded-256x1024   the 64 loops of 256 x 1024 stepped by the paper's own expanded form of the
@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="batched-ragged-256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--runs", type=int, default=128, help="orbits-39: chaotic runs")
+    ap.add_argument("--per-run", type=int, default=2, help="orbits-39: loops cut from each run")
     return ap.parse_args()
 
 
@@ -142,7 +144,7 @@ def main():
     if args.workload.startswith("converge"):
         return bench_converge(args, specs[0])
     if args.workload.startswith("orbits"):
-        return bench_orbits(args)
+        return bench_orbits(args, E=args.runs, per_run=args.per_run)
     if nl == 1 and api.step_form(specs[0].Nx, specs[0].Ns, 1) == "resident":
         return bench_resident(args, cfg, specs[0], steps, dtau, scheme)
     if args.workload.startswith("autograd"):
@@ -602,7 +604,7 @@ def bench_converge(args, spec, dtau=0.05, J_tol=1e-10, stride=100):
 PAPER_PERIODS = [25.37, 53.13, 76.61, 106.98, 123.37, 147.42]
 
 
-def bench_orbits(args, E=64, per_run=2, chunk=400_000, J_tol=5e-25):
+def bench_orbits(args, E=128, per_run=2, chunk=400_000, J_tol=5e-25):
     """Initial loops from chaotic runs (Sec. 4.3) driven to periodic orbits (Sec. 4.4).
 
     The runs: E centre-symmetric KS runs at L = 39 on 64 modes (ETDRK4, dt = 0.05), started
