@@ -139,9 +139,10 @@ def test_recurrences_cap(il):
     assert [tuple(p) for p in pairs.cpu().numpy()[0]] == want[:7]
 
 
-def test_segments_match_oracle(il):
-    L, Nx, dt, every = 39.0, 64, 0.05, 2
-    rng = np.random.default_rng(4)
+@pytest.mark.parametrize("Nx,Ns,kc", [(64, 64, 12), (32, 128, 20), (128, 32, 10), (16, 8, 2)])
+def test_segments_match_oracle(il, Nx, Ns, kc):
+    L, dt, every = 39.0, 0.05, 2
+    rng = np.random.default_rng(4 + Nx)
     u0 = np.stack([loopgen.random_ks_state(rng, Nx, scale=0.5, odd=o) for o in (True, False)])
     snaps_o = [D.integrate(u0[r], L, dt, 1200, every, symmetric=(r == 0))[2] for r in range(2)]
     ns = snaps_o[0].shape[0]
@@ -151,7 +152,6 @@ def test_segments_match_oracle(il):
     dt_s = dt * every
     triples = [(0, 10, 290), (1, 0, 600), (1, 57, 100), (0, 3, 48), (1, 599, 600), (2, 0, 100), (0, 500, 601),
                (0, -1, 100), (1, 20, 40)]
-    Ns, kc = 64, 12
     loops, T = il.ks_segments_to_loops(snaps, ns, torch.tensor(triples, dtype=torch.int32, device=DEV), dt_s, Ns, kc)
     loops, T = loops.cpu().numpy(), T.cpu().numpy()
     for l, (r, a, b) in enumerate(triples):
