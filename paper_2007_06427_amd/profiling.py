@@ -108,8 +108,45 @@ def summarize_traffic(fetch_csv: str, write_csv: str, workload: str, command: st
     open(os.path.join(ROOT, "profiles", f"traffic_{workload}.md"), "w").write("\n".join(lines) + "\n")
 
 
+def summarize_counters(p1_csv: str, p2_csv: str, workload: str, command: str) -> None:
+    """SQ counters of the per-pass kernels from two --pmc runs (wave-cycle fractions from the
+    first, instruction counts and LDS bank-conflict cycles from the second), per kernel at its
+    largest grid, averaged over dispatches."""
+    def load(path):
+        acc = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in csv.DictReader(open(path)):
+            acc[(short_name(r["Kernel_Name"]), int(r["Grid_Size"]))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in acc.items()}
+    a, b = load(p1_csv), load(p2_csv)
+    best = {}
+    for (k, g) in set(a) & set(b):
+        if k.startswith("k_rag") and (k not in best or g > best[k]):
+            best[k] = g
+    lines = [f"# SQ counters per dispatch: {workload}", "",
+             f"Two counter runs of: `{command}`, the first with `--pmc SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
+             "SQ_WAIT_INST_LDS SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VMEM "
+             "SQ_WAVES`, the second with `--pmc SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_LDS_ADDR_CONFLICT "
+             "SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INST_LEVEL_LDS SQ_LDS_UNALIGNED_STALL`.", "",
+             f"Kernel source digest: `{source_digest()}`", "",
+             "Fractions are of SQ_WAVE_CYCLES. Conflict cycles are summed over the chip.", "",
+             "| kernel | grid | waves | VALU active | LDS active | waiting (any) | waiting (LDS) | LDS insts | "
+             "VALU insts | LDS conflict cycles | conflict cycles / LDS inst |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for k in sorted(best):
+        A, B = a[(k, best[k])], b[(k, best[k])]
+        wc = max(A.get("SQ_WAVE_CYCLES", 0.0), 1.0)
+        li = B.get("SQ_INSTS_LDS", 0.0)
+        lines.append(f"| `{k}` | {best[k]} | {A.get('SQ_WAVES', 0):.0f} | {A.get('SQ_ACTIVE_INST_VALU', 0) / wc:.2f} | "
+                     f"{A.get('SQ_ACTIVE_INST_LDS', 0) / wc:.2f} | {A.get('SQ_WAIT_INST_ANY', 0) / wc:.2f} | "
+                     f"{A.get('SQ_WAIT_INST_LDS', 0) / wc:.2f} | {li:.3g} | {B.get('SQ_INSTS_VALU', 0):.3g} | "
+                     f"{B.get('SQ_LDS_BANK_CONFLICT', 0):.3g} | {B.get('SQ_LDS_BANK_CONFLICT', 0) / max(li, 1):.1f} |")
+    open(os.path.join(ROOT, "profiles", f"counters_{workload}.md"), "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
-    if sys.argv[1] == "trace":
+    if sys.argv[1] == "counters":
+        summarize_counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+    elif sys.argv[1] == "trace":
         summarize_trace(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
     elif sys.argv[1] == "traffic":
         summarize_traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
