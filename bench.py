@@ -23,6 +23,8 @@ Workloads:
                       reports the periods of the orbits found beside the paper's
   expanded-256x1024   the 64 loops of 256 x 1024 stepped by the paper's own expanded form of the
                       flow (eq. KS_G_1, loop_step_expanded), with loop_step beside it
+  ks-dns-4096         the chaotic runs of the initial-loop pipeline alone: 4096 centre-symmetric
+                      KS runs at L = 39 on 64 modes, ETDRK4 with dt = 0.05, sampled every 2 steps
   plain-64x128        one 64 x 128 loop, L = 22, IMEX
   plain-32x32         one 32 x 32 loop, L = 22, explicit Euler
 
@@ -56,6 +58,7 @@ WORKLOADS = {
     "plain-32x32": 1,
     "converge-32x32": 1,
     "orbits-39": 1,
+    "ks-dns-4096": 1,
 }
 
 
@@ -145,6 +148,8 @@ def main():
         return bench_converge(args, specs[0])
     if args.workload.startswith("orbits"):
         return bench_orbits(args, E=args.runs, per_run=args.per_run)
+    if args.workload.startswith("ks-dns"):
+        return bench_dns(args)
     if nl == 1 and api.step_form(specs[0].Nx, specs[0].Ns, 1) == "resident":
         return bench_resident(args, cfg, specs[0], steps, dtau, scheme)
     if args.workload.startswith("autograd"):
@@ -670,7 +675,16 @@ def bench_orbits(args, E=128, per_run=2, chunk=400_000, J_tol=5e-25):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded chaotic KS runs)",
         "config": {"workload": args.workload, "runs": E, "loops": nl, "shapes": [[64, 64]], "L": L, "scheme": "imex",
                    "dtau": 0.15, "J_tol": J_tol, "form": api.step_form(64, 64, nl), "parallelism": "none (1 GPU)"},
-        "roofline": None, "cpu_baseline": None,
+        # the loop dynamics run in the resident form: one block per loop, bound by FP64 arithmetic
+        # and LDS latency on the CU each loop occupies
+        "roofline": {"bound": "alu", "achieved": round(step_flops(64, 64) * nl * done / t_conv / 1e12, 3),
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(step_flops(64, 64) * nl * done / t_conv / 1e12 / FP64_PEAK_TFLOPS, 4),
+                     "traffic": None, "kernel": "k_resident<64, 64>", "flops_per_step": step_flops(64, 64),
+                     "cus_used": min(nl, CUS),
+                     "frac_of_cus_used": round(step_flops(64, 64) * nl * done / t_conv / 1e12
+                                               / (FP64_PEAK_TFLOPS * min(nl, CUS) / CUS), 4)},
+        "cpu_baseline": None,
         "pipeline": {"seconds": round(t_pipe, 3), "run_steps_per_s": E * 24000 / t_pipe,
                      "T0_range": [round(float(T0.min()), 2), round(float(T0.max()), 2)]},
         "orbits": {"converged_below_J_tol": int(np.sum(steps >= 0)),
@@ -680,6 +694,63 @@ def bench_orbits(args, E=128, per_run=2, chunk=400_000, J_tol=5e-25):
                    "paper_periods": PAPER_PERIODS,
                    "paper_periods_matched": [p for p in PAPER_PERIODS
                                              if any(abs(f["T"] - p) < 0.01 for f in found)]},
+    }
+    print(json.dumps(out))
+
+
+def dns_step_flops(Nx):
+    """FP64 flops of one ETDRK4 step of one run (direct transforms, K = (Nx-1)/3 modes): four
+    nonlinear evaluations, each an inverse sum over K modes at Nx points and a forward sum over
+    Nx points for K + 1 modes (4 flops per complex-by-real term), plus the stage combinations
+    (about 40 flops per mode)."""
+    K = (Nx - 1) // 3
+    return 4 * (4 * Nx * K + 4 * Nx * (K + 1)) + 40 * (K + 1)
+
+
+def bench_dns(args, E=4096, Nx=64, L=39.0, dt=0.05, every=2):
+    """ks_integrate alone: E runs advanced together, norms and states sampled every 2 steps.
+    `value` is grid points of the runs advanced per second (Nx per run-step)."""
+    import numpy as np
+    import torch
+
+    import loopgen
+    from paper_2007_06427_amd import api, initial_loops as il
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream()
+    steps = args.steps if args.steps is not None else 4000
+    steps -= steps % every
+    rng = np.random.default_rng(7)
+    u = torch.from_numpy(np.stack([loopgen.random_ks_state(rng, Nx, scale=0.1, odd=True) for _ in range(E)])).to(dev)
+    il.ks_integrate(u, L, dt, 2000, 2000, True)  # transient, untimed
+    ns = steps // every
+    norms = torch.empty(E, ns, dtype=torch.float64, device=dev)
+    snaps = torch.empty(E, ns, Nx // 2 + 1, dtype=torch.complex128, device=dev)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    il.ks_integrate(u, L, dt, steps, every, True, norms, snaps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = e0.elapsed_time(e1) * 1e-3
+    n = norms.cpu().numpy()
+    assert np.all(np.isfinite(n)) and n.min() > 1.0, "runs left the chaotic set"
+    fl = dns_step_flops(Nx) * E * steps
+    out = {
+        "metric": "KS run grid points advanced per second (ETDRK4, FP64)",
+        "value": Nx * E * steps / wall, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": 2000,
+        "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded chaotic KS runs)",
+        "config": {"workload": args.workload, "runs": E, "Nx": Nx, "L": L, "dt": dt, "sample_every": every,
+                   "symmetric": True, "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "alu", "achieved": round(fl / gpu_s / 1e12, 3), "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(fl / gpu_s / 1e12 / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": f"k_ks_etdrk4<{Nx}>", "flops_per_run_step": dns_step_flops(Nx),
+                     "avg_launch_us": round(gpu_s * 1e6, 1),
+                     "sample_bytes": int(E * ns * (8 + 16 * (Nx // 2 + 1)))},
+        "cpu_baseline": None,
+        "norm_range": [float(n.min()), float(n.max())],
     }
     print(json.dumps(out))
 

@@ -76,19 +76,25 @@ __device__ Etd etd_coeffs(int j, double L, double h) {
 }
 
 // Per-run LDS: the band spectrum (K+1 complex), the grid (NX reals), the twiddles
-// e^{2 pi i m / NX} (NX complex).
+// e^{2 pi i m / NX} (NX complex), and the partial sums of the forward transform.
+// The forward transform is split into S segments of the grid per mode, so that S (K+1)
+// lanes share its NX (K+1) terms instead of K+1 lanes.
 template <int NX>
 struct Dns {
     static constexpr int K = (NX - 1) / 3;
     static constexpr int H = NX / 2 + 1;
     static constexpr int R = (K + 1 + 63) / 64;  // modes per lane
     static constexpr int P = (NX + 63) / 64;     // grid points per lane
+    static constexpr int S = (2 * (K + 1) <= 64) ? (4 * (K + 1) <= 64 ? (8 * (K + 1) <= 64 ? 8 : 4) : 2) : 1;
+    static constexpr int SEG = NX / S;           // grid points per segment
+    static constexpr int WI = S * (K + 1);       // (segment, mode) partial sums
+    static constexpr int RF = (WI + 63) / 64;    // partial sums per lane
 };
 
 // N_hat_j = -(i q_j / 2) FFT(u^2)_j for the lane's modes, from the lane's band values v.
 template <int NX>
 __device__ __forceinline__ void nonlinear(const cd (&v)[Dns<NX>::R], const Etd (&co)[Dns<NX>::R], cd (&out)[Dns<NX>::R],
-                                          cd* spec, double* grid, const cd* tw) {
+                                          cd* spec, double* grid, const cd* tw, cd* part) {
     using D = Dns<NX>;
     const int lane = threadIdx.x;
 #pragma unroll
@@ -113,23 +119,40 @@ __device__ __forceinline__ void nonlinear(const cd (&v)[Dns<NX>::R], const Etd (
         }
     }
     __syncthreads();
-    // W_j = (1/NX) sum_m grid_m e^{-2 pi i j m / NX}, N_j = -(i q_j / 2) W_j
+    // W_j = (1/NX) sum_m grid_m e^{-2 pi i j m / NX}: partial sums over segments of m, then
+    // their sum in segment order; N_j = -(i q_j / 2) W_j
 #pragma unroll
-    for (int r = 0; r < D::R; ++r) {
-        const int j = lane + 64 * r;
-        double wx = 0.0, wy = 0.0;
-        if (j <= D::K) {
-            for (int m = 0; m < NX; ++m) {
+    for (int rr = 0; rr < D::RF; ++rr) {
+        const int wi = lane + 64 * rr;
+        if (wi < D::WI) {
+            const int sg = wi / (D::K + 1), j = wi % (D::K + 1);
+            double wx = 0.0, wy = 0.0;
+            for (int m = sg * D::SEG; m < (sg + 1) * D::SEG; ++m) {
                 const double g = grid[m];
                 const cd w = tw[(j * m) & (NX - 1)];
                 wx += g * w.x;
                 wy -= g * w.y;
             }
+            part[wi] = cd{wx, wy};
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < D::R; ++r) {
+        const int j = lane + 64 * r;
+        double wx = 0.0, wy = 0.0;
+        if (j <= D::K) {
+#pragma unroll
+            for (int sg = 0; sg < D::S; ++sg) {
+                const cd pw = part[sg * (D::K + 1) + j];
+                wx += pw.x;
+                wy += pw.y;
+            }
         }
         const double s = 0.5 * co[r].q / NX;
         out[r] = cd{s * wy, -s * wx};
     }
-    __syncthreads();  // spec and grid are free for the next evaluation
+    __syncthreads();  // spec, grid and the partial sums are free for the next evaluation
 }
 
 template <int NX>
@@ -164,6 +187,7 @@ __global__ __launch_bounds__(64) void k_ks_etdrk4(double L, int sym, double h, i
     __shared__ cd spec[D::K + 1];
     __shared__ double grid[NX];
     __shared__ cd tw[NX];
+    __shared__ cd part[D::WI];
     const int lane = threadIdx.x;
     const size_t run = blockIdx.x;
     for (int m = lane; m < NX; m += 64) {
@@ -185,20 +209,20 @@ __global__ __launch_bounds__(64) void k_ks_etdrk4(double L, int sym, double h, i
     for (int i = 0; i < nsteps; ++i) {
         if (i % every == 0) record<NX>(lane, u, L, run * (size_t)stride + i / every, norms, snaps);
         cd Nu[D::R], Na[D::R], Nb[D::R], Nc[D::R], a[D::R], b[D::R], c[D::R];
-        nonlinear<NX>(u, co, Nu, spec, grid, tw);
+        nonlinear<NX>(u, co, Nu, spec, grid, tw, part);
 #pragma unroll
         for (int r = 0; r < D::R; ++r)
             a[r] = cd{co[r].E2 * u[r].x + co[r].Q * Nu[r].x, co[r].E2 * u[r].y + co[r].Q * Nu[r].y};
-        nonlinear<NX>(a, co, Na, spec, grid, tw);
+        nonlinear<NX>(a, co, Na, spec, grid, tw, part);
 #pragma unroll
         for (int r = 0; r < D::R; ++r)
             b[r] = cd{co[r].E2 * u[r].x + co[r].Q * Na[r].x, co[r].E2 * u[r].y + co[r].Q * Na[r].y};
-        nonlinear<NX>(b, co, Nb, spec, grid, tw);
+        nonlinear<NX>(b, co, Nb, spec, grid, tw, part);
 #pragma unroll
         for (int r = 0; r < D::R; ++r)
             c[r] = cd{co[r].E2 * a[r].x + co[r].Q * (2.0 * Nb[r].x - Nu[r].x),
                       co[r].E2 * a[r].y + co[r].Q * (2.0 * Nb[r].y - Nu[r].y)};
-        nonlinear<NX>(c, co, Nc, spec, grid, tw);
+        nonlinear<NX>(c, co, Nc, spec, grid, tw, part);
 #pragma unroll
         for (int r = 0; r < D::R; ++r) {
             const Etd& e = co[r];
