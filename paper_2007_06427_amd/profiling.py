@@ -7,14 +7,13 @@
 WRITE_SIZE in the other, both in KiB per dispatch. It scales each counter by its reading for a
 plain device copy of known size. bench.py runs a 64 MiB device copy for this, so a
 calibrated counter reads 65536 KiB for that copy. It then writes
-profiles/traffic_<workload>.{json,md}, stamped with a digest of the kernel sources; bench.py
-uses the bytes only while the sources are unchanged.
+profiles/traffic_<workload>.{json,md}, stamped with a digest of the sources of the workload's translation unit (the file and the
+project headers it includes); bench.py uses the bytes only while those are unchanged.
 """
 from __future__ import annotations
 
 import collections
 import csv
-import glob
 import hashlib
 import json
 import os
@@ -26,11 +25,36 @@ ROOT = os.path.dirname(HERE)
 COPY_BYTES = 64 << 20
 
 
-def source_digest() -> str:
+def _unit_files(unit: str):
+    """The translation unit csrc/<unit> and every kernel header (csrc/) it includes, recursively.
+    The C-ABI headers under include/ hold declarations only and are left out."""
+    dirs = [os.path.join(HERE, "csrc")]
+    seen, todo = [], [os.path.join(HERE, "csrc", unit)]
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.append(f)
+        for inc in re.findall(r'^#include "([^"]+)"', open(f).read(), flags=re.M):
+            for d in dirs:
+                if os.path.exists(os.path.join(d, inc)):
+                    todo.append(os.path.join(d, inc))
+                    break
+    return sorted(seen)
+
+
+def source_digest(unit: str = "looporbit.hip") -> str:
+    """Digest of the sources that make one translation unit's kernels (the loop dynamics by
+    default; ksdns.hip for the initial-loop pipeline)."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+    for f in _unit_files(unit):
+        h.update(os.path.basename(f).encode())
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
+
+
+def unit_of(workload: str) -> str:
+    return "ksdns.hip" if workload.startswith("ks-dns") else "looporbit.hip"
 
 
 def short_name(name: str) -> str:
@@ -42,7 +66,7 @@ def summarize_trace(stats_csv: str, out_md: str, workload: str, command: str) ->
     rows = list(csv.DictReader(open(stats_csv)))
     lines = [f"# Kernel durations: {workload}", "",
              f"Command (run from the repository root, with `TMPDIR=/tmp`): `{command}`", "",
-             f"Kernel source digest: `{source_digest()}`", "",
+             f"Kernel source digest: `{source_digest(unit_of(workload))}`", "",
              "| kernel | calls | avg us | total ms | % of GPU time |", "|---|---:|---:|---:|---:|"]
     for r in rows:
         lines.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
@@ -88,7 +112,7 @@ def summarize_traffic(fetch_csv: str, write_csv: str, workload: str, command: st
         b = (f / ffac + w / wfac) * 1024
         kernels[name] = {"grid": int(key[1]), "fetch_kib": round(f, 1), "write_kib": round(w, 1),
                          "bytes_per_launch": round(b), "dispatches": min(len(fetch[key]), len(write[key]))}
-    out = {"workload": workload, "command": command, "source_digest": source_digest(),
+    out = {"workload": workload, "command": command, "source_digest": source_digest(unit_of(workload)),
            "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": fcopy, "write_kib": wcopy,
                                 "fetch_factor": ffac, "write_factor": wfac},
            "kernels": kernels}
@@ -98,7 +122,7 @@ def summarize_traffic(fetch_csv: str, write_csv: str, workload: str, command: st
              f"Two counter runs of: `{command}` with `--pmc FETCH_SIZE`, then `--pmc WRITE_SIZE`.", "",
              f"Calibration: a {COPY_BYTES >> 20} MiB device copy read FETCH_SIZE {fcopy} KiB and WRITE_SIZE {wcopy} KiB "
              f"(factors {ffac:.3f}, {wfac:.3f}); kernel readings are divided by these.", "",
-             f"Kernel source digest: `{source_digest()}`", "",
+             f"Kernel source digest: `{source_digest(unit_of(workload))}`", "",
              "Per kernel: the launches over every loop (largest grid) found in both runs.", "",
              "| kernel | grid (work-items) | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | calibrated bytes / launch |",
              "|---|---:|---:|---:|---:|---:|"]
@@ -127,7 +151,7 @@ def summarize_counters(p1_csv: str, p2_csv: str, workload: str, command: str) ->
              "SQ_WAIT_INST_LDS SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VMEM "
              "SQ_WAVES`, the second with `--pmc SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_LDS_ADDR_CONFLICT "
              "SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INST_LEVEL_LDS SQ_LDS_UNALIGNED_STALL`.", "",
-             f"Kernel source digest: `{source_digest()}`", "",
+             f"Kernel source digest: `{source_digest(unit_of(workload))}`", "",
              "Fractions are of SQ_WAVE_CYCLES. Conflict cycles are summed over the chip.", "",
              "| kernel | grid | waves | VALU active | LDS active | waiting (any) | waiting (LDS) | LDS insts | "
              "VALU insts | LDS conflict cycles | conflict cycles / LDS inst |",
