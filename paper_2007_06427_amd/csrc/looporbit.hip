@@ -971,6 +971,23 @@ void launch_from_band(const Shape& s, const cd* src, cd* out, hipStream_t st) {
     hipLaunchKernelGGL(k_from_band, grid, dim3(256), 0, st, s, src, out);
 }
 
+// Raise kernel k's dynamic-LDS limit to `bytes` on the current device, once: the setting is
+// host-side state, so later calls (also those recorded into a HIP graph) make no runtime call.
+int ensure_lds_limit(const void* k, size_t bytes) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LOOP_EHIP;
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, size_t> done;
+    std::lock_guard<std::mutex> g(mu);
+    const auto key = std::make_pair(k, dev);
+    const auto it = done.find(key);
+    if (it != done.end() && it->second >= bytes) return LOOP_OK;
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+        return LOOP_EHIP;
+    done[key] = bytes;
+    return LOOP_OK;
+}
+
 // ---------------------------------------------------------------------------- expanded form
 // The row pass keeps two input tiles and the exchange regions apart in LDS (up to 83 KB),
 // so it takes dynamic LDS; rows of up to 512 points.
@@ -980,11 +997,7 @@ int launch_xB(const Shape& s, const Work& w, const double* T, const cd* tw, hipS
         constexpr int M = decltype(c)::value;
         constexpr size_t bytes = XRowG<M>::LDS * sizeof(cd);
         auto k = k_xB<M>;
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)bytes) != hipSuccess) {
-            rc = LOOP_EHIP;
-            return;
-        }
+        if ((rc = ensure_lds_limit(reinterpret_cast<const void*>(k), bytes))) return;
         hipLaunchKernelGGL(k, dim3(row_blocks(s)), dim3(kBlock), bytes, st, s, w, T, tw);
         rc = LOOP_OK;
     });
@@ -1116,8 +1129,7 @@ int launch_resident(const Shape& s, cd* u, double* T, double dtau, int scheme, i
             using R = ResG<M_, N_>;
             if constexpr (R::FITS) {
                 auto k = k_resident<M_, N_>;
-                hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)R::BYTES);
+                if ((st = ensure_lds_limit(reinterpret_cast<const void*>(k), R::BYTES))) return;
                 hipLaunchKernelGGL(k, dim3(s.nloops), dim3(kBlock), R::BYTES, hs, s, u, u, T, dtau, scheme, nsteps,
                                    J_hist, status, tw);
                 st = last_error();
