@@ -122,7 +122,7 @@ def measured_traffic(workload, kernel):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch
