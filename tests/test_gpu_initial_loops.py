@@ -179,3 +179,23 @@ def test_pipeline_gives_centre_symmetric_loops(il):
         assert np.max(np.abs(lo[l] + np.conj(lo[l][kneg, :]))) <= 1e-15 * np.max(np.abs(lo[l]))
         uo, To = D.segment_to_loop(sn[r], a, b, dt * every, 64, 10)
         assert rel(lo[l], uo) < 1e-13
+
+
+def test_binding_rejects_bad_arguments(il):
+    from paper_2007_06427_amd import LoopOrbitError
+    u = torch.zeros(2, 33, dtype=torch.complex128, device=DEV)
+    n = torch.zeros(2, 10, dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError):  # a CPU tensor
+        il.ks_integrate(torch.zeros(2, 33, dtype=torch.complex128), 39.0, 0.05, 8)
+    with pytest.raises(ValueError):  # the samples of the call do not fit after first_sample
+        il.ks_integrate(u, 39.0, 0.05, 40, 4, norms=n, first_sample=1)
+    with pytest.raises(ValueError):  # one row per run
+        il.ks_integrate(u, 39.0, 0.05, 8, 4, norms=torch.zeros(3, 10, dtype=torch.float64, device=DEV))
+    with pytest.raises(LoopOrbitError):  # 512-point runs are not compiled in
+        il.ks_integrate(torch.zeros(1, 257, dtype=torch.complex128, device=DEV), 39.0, 0.05, 8)
+    with pytest.raises(LoopOrbitError):  # sample_every does not divide nsteps
+        il.ks_integrate(u, 39.0, 0.05, 10, 4)
+    with pytest.raises(LoopOrbitError):  # kc beyond the loop band
+        il.ks_segments_to_loops(torch.zeros(1, 10, 33, dtype=torch.complex128, device=DEV), 10,
+                                torch.zeros(1, 3, dtype=torch.int32, device=DEV), 0.1, 16, 6)
+    assert torch.equal(u, torch.zeros_like(u))  # nothing ran
