@@ -181,8 +181,9 @@ int loop_converge(double L, int Nx, int Ns, int nloops, double* T, double* uhat,
  * with nloops = 1) bit for bit; with nloops > 1 and Ns below the row-tile height the two pair
  * rows of different loops differently in the row transforms and agree to rounding.
  * loop_set_resident(mode) sets the choice for later calls in this process: 0 per-pass always,
- * 1 (default) resident where it was measured faster (at most one loop per CU, and for shapes
- * whose passes take two rounds per block, at least 16 loops), 2 resident wherever it exists.
+ * 1 (default) resident where it was measured faster (for shapes whose passes take one round
+ * per block, up to two loops per CU; for the others, up to one loop per CU and at least 16
+ * loops), 2 resident wherever it exists.
  * It returns the previous mode, or LOOP_EINVAL for other values.
  * loop_resident_supported returns 1 when the resident form exists for an Nx x Ns loop on the
  * current device, else 0. loop_step_form returns the form loop_step takes for nloops loops of

@@ -1116,8 +1116,12 @@ bool resident_preferred(int Nx, int Ns, int nloops) {
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return false;
-    if (nloops > cus) return false;
-    return resident_one_round(Nx, Ns) || nloops >= 16;
+    // Loops beyond one per CU take further rounds of the resident launch. Measured against
+    // the per-pass form, one-round shapes (32 x 32, 64 x 64) stay ahead for two rounds of
+    // loops, two-round shapes only within one round and with at least 16 loops.
+    const int rounds = (nloops + cus - 1) / cus;
+    if (resident_one_round(Nx, Ns)) return rounds <= 2;
+    return rounds == 1 && nloops >= 16;
 }
 
 int launch_resident(const Shape& s, cd* u, double* T, double dtau, int scheme, int nsteps, double* J_hist,
