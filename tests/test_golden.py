@@ -51,3 +51,31 @@ def test_oracle_trajectory_regression_plain32x32():
     assert abs(T - g["T_final"]) <= 1e-12 * abs(T)
     for j, k, re, im in g["uhat_final_band"]:
         assert abs(u[k % spec.Ns, j] - complex(re, im)) <= 1e-12 * (1 + abs(complex(re, im)))
+
+
+def _orbit_fixture():
+    path = os.path.join(HERE, "oracle_orbit_L39.json")
+    return json.load(open(path))
+
+
+def _spectrum(modes, Nx, Ns):
+    u = np.zeros((Ns, Nx // 2 + 1), dtype=np.complex128)
+    for j, k, re, im in modes:
+        u[k % Ns, j] = complex(re, im)
+    return u
+
+
+def test_oracle_orbit_is_the_papers_shortest_orbit():
+    """tests/golden/make_orbit.py cuts loops from the oracle's own chaotic runs at L = 39 and
+    drives them with the oracle's loop dynamics (Sec. 4.3-4.4). The stored converged loop is a
+    periodic orbit by the oracle's own residual, and its period is the shortest one the paper
+    reports, T = 25.37 (Fig. 5a)."""
+    g = _orbit_fixture()
+    u = _spectrum(g["uhat_final_band"], g["Nx"], g["Ns"])
+    J = K.cost(u, g["T_final"], g["L"])
+    assert J < 1e-19 and abs(J - g["J_final"]) <= 1e-6 * g["J_final"] + 1e-30
+    assert abs(g["T_final"] - 25.37) < 0.005
+    # it varies along s (not an equilibrium) and is centre-symmetric like its initial loop
+    assert np.sum(np.abs(u[1:]) ** 2) > 1e-3 * np.sum(np.abs(u) ** 2)
+    kneg = (-np.arange(g["Ns"])) % g["Ns"]
+    assert np.max(np.abs(u + np.conj(u[kneg, :]))) < 1e-12 * np.max(np.abs(u))
