@@ -10,7 +10,9 @@ Sec. 4.4, J examined every 1000 steps, J < 1e-20). The first loop that converges
 its initial spectrum, and its converged period, cost, step and extrapolation counts and state
 (a loop at the paper's T = 25.37 first, if one converged there).
 
-    python tests/golden/make_orbit.py            (about 10 minutes on 8 cores)
+    python tests/golden/make_orbit.py            (about 15 minutes on 8 cores)
+    python tests/golden/make_orbit.py LO HI TARGET MAX_STEPS OUT.json
+        (another window of initial periods, preferring an orbit at period TARGET)
 """
 from __future__ import annotations
 
@@ -32,6 +34,11 @@ from oracle import ks_loop as K  # noqa: E402
 L, NX, DT, EVERY, NS, KC = 39.0, 64, 0.05, 2, 64, 10
 DTAU, J_TOL, STRIDE, MAX_STEPS = 0.15, 1e-20, 1000, 800_000
 T_WINDOW = (23.0, 28.0)
+TARGET = 25.37
+OUT = "oracle_orbit_L39.json"
+if len(sys.argv) == 6:
+    T_WINDOW = (float(sys.argv[1]), float(sys.argv[2]))
+    TARGET, MAX_STEPS, OUT = float(sys.argv[3]), int(sys.argv[4]), sys.argv[5]
 
 
 def run_candidates(r_u0):
@@ -65,8 +72,8 @@ def main():
     done = [(res, c) for res, c in zip(results, pick) if res[6] < J_TOL]
     if not done:
         raise SystemExit("no loop converged")
-    # prefer the orbit the paper reports at T = 25.37 (Fig. 5) if one of them reached it
-    done.sort(key=lambda rc: abs(rc[0][5] - 25.37) > 0.02)
+    # prefer the orbit the paper reports at T = TARGET (Fig. 5) if one of them reached it
+    done.sort(key=lambda rc: abs(rc[0][5] - TARGET) > 0.02)
     (r, a, b, T0, u, T, J, steps, ex), c = done[0]
     loop = c[3]
     Kx, Ks = K.band_limits(NX, NS)
@@ -80,7 +87,7 @@ def main():
         "run": r, "samples": [a, b], "T0": T0, "uhat0_modes": init,
         "T_final": T, "J_final": J, "steps": steps, "extrapolations": ex, "uhat_final_band": final,
     }
-    json.dump(out, open(os.path.join(HERE, "oracle_orbit_L39.json"), "w"))
+    json.dump(out, open(os.path.join(HERE, OUT), "w"))
     print(f"stored run {r}: T = {T:.6f}", flush=True)
 
 
