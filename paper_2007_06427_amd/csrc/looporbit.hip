@@ -632,7 +632,7 @@ __device__ __forceinline__ const cd* per_pass(const cd* tw) {
 // intermediates in LDS. The rfft-layout spectrum is read at the start and written back at
 // the end (the same arithmetic as k_to_band and k_from_band), T[l] likewise.
 template <int M, int N>
-__global__ __launch_bounds__(kBlock) void k_resident(Shape sh, const cd* uin, cd* uout, double* T, double dtau,
+__global__ __launch_bounds__(kBlock, (ResG<M, N>::BLOCKS_PER_CU)) void k_resident(Shape sh, const cd* uin, cd* uout, double* T, double dtau,
                                                      int scheme, int nsteps, double* J_hist, int* status,
                                                      const cd* __restrict__ tw) {
     using R = ResG<M, N>;
@@ -1111,14 +1111,27 @@ bool resident_one_round(int Nx, int Ns) {
 // latency-bound; the per-pass form spreads a pass over more CUs but pays HBM round trips):
 // resident wins while every loop gets a CU of its own (nloops up to the CU count), except a
 // lone loop or a few loops whose passes need two rounds per block (32 x 256, 64 x 128).
+int resident_blocks_per_cu(int Nx, int Ns) {
+    int b = 1;
+    host_size_switch<8, 128>(Nx, [&](auto m) {
+        host_size_switch<8, 512>(Ns, [&](auto n) {
+            using R = ResG<decltype(m)::value, decltype(n)::value>;
+            if constexpr (R::FITS) b = R::BLOCKS_PER_CU;
+        });
+    });
+    return b;
+}
+
 bool resident_preferred(int Nx, int Ns, int nloops) {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return false;
-    // Loops beyond one per CU take further rounds of the resident launch. Measured against
-    // the per-pass form, one-round shapes (32 x 32, 64 x 64) stay ahead for two rounds of
-    // loops, two-round shapes only within one round and with at least 16 loops.
+    cus *= resident_blocks_per_cu(Nx, Ns);  // resident blocks the chip holds at once
+    // Loops beyond the blocks the chip holds at once take further rounds of the resident
+    // launch. Measured against the per-pass form, one-round shapes (32 x 32, 64 x 64) stay
+    // ahead for two rounds of loops, two-round shapes only within one round and with at least
+    // 16 loops.
     const int rounds = (nloops + cus - 1) / cus;
     if (resident_one_round(Nx, Ns)) return rounds <= 2;
     return rounds == 1 && nloops >= 16;

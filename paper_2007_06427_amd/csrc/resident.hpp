@@ -44,6 +44,10 @@ struct ResG {
     static constexpr int DOUBLES = 2 * C + 12;
     static constexpr size_t BYTES = sizeof(cd) * (size_t)(S + 2 * W + EX) + sizeof(double) * DOUBLES;
     static constexpr bool FITS = BYTES <= 160 * 1024 && N <= 512 && M <= 128;
+    // Two blocks share a CU where both fit its LDS; the kernel is then compiled for two
+    // wavefronts per SIMD (at most 256 registers each, a few spilled), which costs a lone
+    // block 5-8% but lets a second loop hide the first one's latency.
+    static constexpr int BLOCKS_PER_CU = BYTES <= 80 * 1024 ? 2 : 1;
     static constexpr int COL_ROUNDS = (C + ColG<N>::F - 1) / ColG<N>::F;
     static constexpr int ROW_ROUNDS = (N + RowG<M>::ROWS - 1) / RowG<M>::ROWS;
 };
