@@ -11,7 +11,7 @@ its initial spectrum, and its converged period, cost, step and extrapolation cou
 (a loop at the paper's T = 25.37 first, if one converged there).
 
     python tests/golden/make_orbit.py            (about 15 minutes on 8 cores)
-    python tests/golden/make_orbit.py LO HI TARGET MAX_STEPS OUT.json
+    python tests/golden/make_orbit.py LO HI TARGET MAX_STEPS OUT.json [J_TOL]
         (another window of initial periods, preferring an orbit at period TARGET)
 """
 from __future__ import annotations
@@ -36,9 +36,11 @@ DTAU, J_TOL, STRIDE, MAX_STEPS = 0.15, 1e-20, 1000, 800_000
 T_WINDOW = (23.0, 28.0)
 TARGET = 25.37
 OUT = "oracle_orbit_L39.json"
-if len(sys.argv) == 6:
+if len(sys.argv) in (6, 7):
     T_WINDOW = (float(sys.argv[1]), float(sys.argv[2]))
     TARGET, MAX_STEPS, OUT = float(sys.argv[3]), int(sys.argv[4]), sys.argv[5]
+    if len(sys.argv) == 7:
+        J_TOL = float(sys.argv[6])
 
 
 def run_candidates(r_u0):
