@@ -272,7 +272,8 @@ int loop_batch_store(const void* plan, double* uhat_pool, void* ws, size_t ws_by
  * loop_batch_autotune times, on the caller's state (T[nloops], uhat_pool as for
  * loop_batch_step; neither is modified), every usable variant of every pass over `reps`
  * back-to-back launches (best of three trials, hipEvent timing on `stream`), keeps the
- * fastest per pass, then times `reps` whole steps of each schedule (the multi-stream one with
+ * fastest per pass (the plan's current variant unless another is faster by more than 1%),
+ * then times `reps` whole steps of each schedule (the multi-stream one with
  * 2, 3 and 4 streams) and keeps the fastest. The work of every kernel is independent of dtau
  * and scheme, so the timing runs use a step of 1e-30 (IMEX), which leaves the state unchanged
  * to the last bit in practice and keeps every repetition finite. It allocates temporary

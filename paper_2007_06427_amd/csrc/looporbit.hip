@@ -2061,7 +2061,8 @@ int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, in
     const BatchArgs a = batch_args(p, base, tT, nullptr, 2, dtau, scheme, tw);
     for (int pass = PASS_A; pass <= PASS_E; ++pass) launch_pass(p, pass, 0, a, hs);
     for (int pass = PASS_A; pass <= PASS_E; ++pass) {
-        int best_v = p->variant[pass];
+        const int incumbent = p->variant[pass];
+        int best_v = incumbent;
         double best_t = 1e300;
         for (int v = 0; v < rag_count(pass); ++v) {
             if (!rag_covers(p, pass, v)) continue;
@@ -2074,6 +2075,10 @@ int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, in
                 best_v = v;
             }
         }
+        // the plan's current variant stays unless another is faster by more than 1%, so that
+        // timing noise between near-equal variants does not flip the choice from run to run
+        const double t_inc = rep[pass * kRagVariants + incumbent];
+        if (best_v != incumbent && t_inc > 0.0 && best_t > 0.99 * t_inc) best_v = incumbent;
         p->variant[pass] = best_v;
     }
     // schedules: per-pass, persistent, then the multi-stream one with 2, 3 and 4 streams
