@@ -162,7 +162,8 @@ def test_autotune_keeps_state_picks_fastest_and_is_reused(api):
     assert b.status() == 0
     for name, times in rep["pass_us"].items():
         assert len(times) >= 1 and all(t > 0 for t in times.values())
-        assert times[rep["variants"][name]] <= 1.01 * min(times.values()), (name, rep)
+        # the plan's variant stays unless another is faster by more than 1% (times rounded to ns)
+        assert 0.99 * times[rep["variants"][name]] <= min(times.values()) + 1e-3, (name, rep)
     su = rep["step_us"]
     assert set(su) == {"per-pass", "persistent", "streams-2", "streams-3", "streams-4"}
     assert all(v > 0 for v in su.values())
