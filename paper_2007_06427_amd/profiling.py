@@ -71,7 +71,25 @@ def summarize_trace(stats_csv: str, out_md: str, workload: str, command: str) ->
     for r in rows:
         lines.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+    trace_csv = stats_csv.replace("kernel_stats", "kernel_trace")
+    if trace_csv != stats_csv and os.path.exists(trace_csv):
+        lines += _per_grid(trace_csv, [short_name(r["Name"]) for r in rows[:4]])
     open(out_md, "w").write("\n".join(lines) + "\n")
+
+
+def _per_grid(trace_csv: str, kernels) -> list:
+    """Launch durations of the given kernels, split by grid size: a kernel launched over all
+    loops and over groups of them (the streams schedule) has one row per grid."""
+    acc = collections.defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        k = short_name(r["Kernel_Name"])
+        if k in kernels:
+            acc[(k, int(r["Grid_Size_X"]))].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = ["", "Per grid size (work-items), from the kernel trace of the same run:", "",
+             "| kernel | grid | launches | avg us | min us | max us |", "|---|---:|---:|---:|---:|---:|"]
+    for (k, g), v in sorted(acc.items(), key=lambda kv: (kernels.index(kv[0][0]), -kv[0][1])):
+        lines.append(f"| `{k}` | {g} | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} | {max(v):.2f} |")
+    return lines
 
 
 def _per_kernel(counter_csv: str, counter: str):
