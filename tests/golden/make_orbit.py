@@ -1,4 +1,4 @@
-"""Write tests/golden/oracle_orbit_L39.json with the oracle alone (Sec. 4.3-4.4).
+"""Write a converged orbit at L = 39 (tests/golden/oracle_orbit_L39*.json) with the oracle alone (Sec. 4.3-4.4).
 
 The initial-loop pipeline of Sec. 4.3 and the loop dynamics, both from oracle/: centre-symmetric
 chaotic KS runs at L = 39 (64 modes, ETDRK4, dt = 0.05, seeded small odd fields,
@@ -13,6 +13,12 @@ its initial spectrum, and its converged period, cost, step and extrapolation cou
     python tests/golden/make_orbit.py            (about 15 minutes on 8 cores)
     python tests/golden/make_orbit.py LO HI TARGET MAX_STEPS OUT.json [J_TOL]
         (another window of initial periods, preferring an orbit at period TARGET)
+
+The stored fixtures:
+
+    oracle_orbit_L39.json       python tests/golden/make_orbit.py
+    oracle_orbit_L39_T76.json   python tests/golden/make_orbit.py 76.0 76.5 76.61 4000000 oracle_orbit_L39_T76.json 5e-20
+                                (about 65 minutes: three loops of 2.7-3.8 million steps each)
 """
 from __future__ import annotations
 
@@ -84,7 +90,8 @@ def main():
     final = [[j, k, float(u[k % NS, j].real), float(u[k % NS, j].imag)]
              for k in range(-Ks, Ks + 1) for j in range(0, Kx + 1)]
     out = {
-        "recipe": __doc__.strip().splitlines()[0], "L": L, "Nx": NX, "Ns": NS, "dtau": DTAU, "scheme": "imex",
+        "recipe": __doc__.strip().splitlines()[0],
+        "command": " ".join(["python", "tests/golden/make_orbit.py"] + sys.argv[1:]), "L": L, "Nx": NX, "Ns": NS, "dtau": DTAU, "scheme": "imex",
         "J_tol": J_TOL, "stride": STRIDE, "max_steps": MAX_STEPS, "sqrtJ_first": 1e-3,
         "run": r, "samples": [a, b], "T0": T0, "uhat0_modes": init,
         "T_final": T, "J_final": J, "steps": steps, "extrapolations": ex, "uhat_final_band": final,

@@ -43,19 +43,26 @@ def test_pipeline_and_loop_dynamics_find_the_papers_shortest_orbit():
         assert np.max(np.abs(u[i] + np.conj(u[i][kneg, :]))) < 1e-12 * np.max(np.abs(u[i]))
 
 
-def test_device_driver_reaches_the_oracle_orbit():
-    """From the initial loop the oracle cut from its own chaotic runs (tests/golden/
-    oracle_orbit_L39.json, written by make_orbit.py), the device driver with the same settings
-    (IMEX, dtau = 0.15, J examined every 1000 steps, App. C extrapolations, J < 1e-20) takes the
-    oracle's 219 000 steps and 166 extrapolations and reaches the orbit the oracle reached, the
-    paper's T = 25.37: T to 1e-8 and the band-mode magnitudes (which do not depend on the
-    orbit's phase in s) to 1e-8."""
+@pytest.mark.parametrize("name", ["oracle_orbit_L39.json", "oracle_orbit_L39_T76.json"])
+def test_device_driver_reaches_the_oracle_orbit(name):
+    """From the initial loop the oracle cut from its own chaotic runs (tests/golden/, written by
+    make_orbit.py), the device driver with the same settings (IMEX, dtau = 0.15, J examined
+    every 1000 steps, App. C extrapolations, the fixture's J tolerance) takes the oracle's
+    decisions and reaches the orbit the oracle reached: T to 1e-8 and the band-mode magnitudes
+    (which do not depend on the orbit's phase in s) to 1e-8.
+
+    oracle_orbit_L39.json is the paper's T = 25.37 (219 000 steps, 166 extrapolations);
+    oracle_orbit_L39_T76.json is the paper's T = 76.61 (3 806 000 steps, 3384 extrapolations,
+    about a minute on the device). The two sides differ only in round-off, and on these loops no
+    decision on J was close enough to a threshold for that to flip it: the step and extrapolation
+    counts agree exactly. A kernel change that moves round-off could in principle flip one; the
+    orbit comparison below would still hold."""
     import json
     import os
     from paper_2007_06427_amd import api
     torch.cuda.set_device(0)
     api.init()
-    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_orbit_L39.json")))
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)))
     Nx, Ns = g["Nx"], g["Ns"]
     u0 = np.zeros((Ns, Nx // 2 + 1), dtype=np.complex128)
     for j, k, re, im in g["uhat0_modes"]:
@@ -64,7 +71,9 @@ def test_device_driver_reaches_the_oracle_orbit():
     T = torch.tensor([g["T0"]], dtype=torch.float64, device=DEV)
     r = api.loop_converge(u, T, g["L"], g["dtau"], api.IMEX, g["J_tol"], stride=g["stride"],
                           max_steps=g["max_steps"], accelerate=True, sqrtJ_first=g["sqrtJ_first"])
-    # the same decisions: both drivers examine J after every stride and extrapolate on it
+    print(f"{name}: device {r['steps'][0]} steps, {r['extrapolations'][0]} extrapolations; "
+          f"oracle {g['steps']}, {g['extrapolations']}", flush=True)
+    # both drivers examine J after every stride and extrapolate on it
     assert r["steps"][0] == g["steps"] and r["extrapolations"][0] == g["extrapolations"], (r, g["steps"])
     assert r["J"][0] < g["J_tol"]
     assert abs(T.item() - g["T_final"]) <= 1e-8, (T.item(), g["T_final"], r)
