@@ -1668,7 +1668,10 @@ int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns,
     int st = get_table(&tw);
     if (st) return st;
     BatchPlan* p = new BatchPlan();
-    hipGetDevice(&p->device);
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return LOOP_EHIP;
+    }
     p->nloops = nloops;
     p->loops.resize(nloops);
     // work space: header | queue | done[nloops] | per-loop regions
@@ -1896,17 +1899,19 @@ void launch_group_pass(const BatchPlan* p, int g, int pass, int step, const Batc
 // sx[g - 1], each group started one pass after the previous one (after its first pass B), so
 // that the GPU runs different passes of different groups side by side, each as its own
 // kernel with its own registers and LDS. Events fork the plan's streams from the caller's and
-// join them back before the caller's next work.
-void launch_streams(const BatchPlan* p, int nsteps, const BatchArgs& a, hipStream_t hs) {
+// join them back before the caller's next work. Returns LOOP_EHIP if an event could not be
+// recorded or waited on: the groups' order would then not be guaranteed.
+int launch_streams(const BatchPlan* p, int nsteps, const BatchArgs& a, hipStream_t hs) {
     const int K = p->nstreams;
     auto st = [&](int g) { return g == 0 ? hs : p->sx[g - 1]; };
-    hipEventRecord(p->ev_fork, hs);
-    for (int g = 1; g < K; ++g) hipStreamWaitEvent(st(g), p->ev_fork, 0);
+    bool ok = hipEventRecord(p->ev_fork, hs) == hipSuccess;
+    for (int g = 1; g < K; ++g) ok = ok && hipStreamWaitEvent(st(g), p->ev_fork, 0) == hipSuccess;
+    if (!ok) return LOOP_EHIP;
     for (int g = 0; g < K; ++g) {
-        if (g > 0) hipStreamWaitEvent(st(g), p->ev_lag[g - 1], 0);
+        if (g > 0 && hipStreamWaitEvent(st(g), p->ev_lag[g - 1], 0) != hipSuccess) return LOOP_EHIP;
         launch_group_pass(p, g, PASS_A, 0, a, st(g));
         launch_group_pass(p, g, PASS_B, 0, a, st(g));
-        if (g + 1 < K) hipEventRecord(p->ev_lag[g], st(g));
+        if (g + 1 < K && hipEventRecord(p->ev_lag[g], st(g)) != hipSuccess) return LOOP_EHIP;
     }
     // queue the groups' launches in turn, one pass each
     for (int i = 0; i < nsteps; ++i)
@@ -1914,9 +1919,11 @@ void launch_streams(const BatchPlan* p, int nsteps, const BatchArgs& a, hipStrea
             for (int g = 0; g < K; ++g)
                 if (!(i == 0 && pass == PASS_B)) launch_group_pass(p, g, pass, i, a, st(g));
     for (int g = 1; g < K; ++g) {
-        hipEventRecord(p->ev_join[g - 1], st(g));
-        hipStreamWaitEvent(hs, p->ev_join[g - 1], 0);
+        if (hipEventRecord(p->ev_join[g - 1], st(g)) != hipSuccess ||
+            hipStreamWaitEvent(hs, p->ev_join[g - 1], 0) != hipSuccess)
+            return LOOP_EHIP;
     }
+    return LOOP_OK;
 }
 }  // namespace
 
@@ -1975,7 +1982,7 @@ int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau,
             if (total >= (1ll << 31)) return LOOP_EINVAL;
             hipLaunchKernelGGL(k_batch, dim3(p->grid), dim3(kBlock), p->lds_bytes, hs, a);
         } else if (p->schedule == LOOP_BATCH_STREAMS) {
-            launch_streams(p, nsteps, a, hs);
+            if ((st = launch_streams(p, nsteps, a, hs))) return st;
         } else {
             launch_pass(p, PASS_A, 0, a, hs);
             for (int i = 0; i < nsteps; ++i)
@@ -2042,15 +2049,16 @@ int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, in
     }
     std::vector<double> rep(5 * kRagVariants + 5, -1.0);
     // Mean microseconds per call of `launch` over n back-to-back calls, best of three trials.
+    // A failed event call marks the run (timed_ok), and the tuner then reports LOOP_EHIP.
+    bool timed_ok = true;
     auto time_calls = [&](auto&& launch, int n) -> double {
         double best = 1e300;
         for (int trial = 0; trial < 3; ++trial) {
-            hipEventRecord(e0, hs);
+            timed_ok = timed_ok && hipEventRecord(e0, hs) == hipSuccess;
             for (int i = 0; i < n; ++i) launch();
-            hipEventRecord(e1, hs);
-            hipEventSynchronize(e1);
             float ms = 0.0f;
-            hipEventElapsedTime(&ms, e0, e1);
+            timed_ok = timed_ok && hipEventRecord(e1, hs) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                       hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
             best = std::min(best, 1e3 * (double)ms / n);
         }
         return best;
@@ -2088,11 +2096,14 @@ int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, in
         const int sc = c < 2 ? c : LOOP_BATCH_STREAMS, k = c < 2 ? 2 : c;
         p->schedule = sc;
         p->nstreams = k;
-        loop_batch_step(p, tT, tpool, dtau, scheme, 1, nullptr, ws, ws_bytes, stream);
-        const double us =
-            time_calls([&] { loop_batch_step(p, tT, tpool, dtau, scheme, reps, nullptr, ws, ws_bytes, stream); },
-                       1) /
-            reps;
+        timed_ok = timed_ok && loop_batch_step(p, tT, tpool, dtau, scheme, 1, nullptr, ws, ws_bytes, stream) == 0;
+        const double us = time_calls(
+                              [&] {
+                                  timed_ok = timed_ok && loop_batch_step(p, tT, tpool, dtau, scheme, reps, nullptr,
+                                                                         ws, ws_bytes, stream) == 0;
+                              },
+                              1) /
+                          reps;
         rep[5 * kRagVariants + c] = us;
         if (us < best_us) {
             best_us = us;
@@ -2103,7 +2114,7 @@ int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, in
     p->schedule = best_s;
     p->nstreams = best_k;
     st = last_error();
-    if (hipStreamSynchronize(hs) != hipSuccess) st = LOOP_EHIP;
+    if (hipStreamSynchronize(hs) != hipSuccess || !timed_ok) st = LOOP_EHIP;
     release();
     if (st) return st;
     st = loop_status_sync(ws, stream);
