@@ -144,6 +144,12 @@ def main():
     api.init()
     dev = "cuda:0"
     stream = torch.cuda.current_stream()
+    # A plain device copy of known size, before any other copy of the run: its counter
+    # readings calibrate FETCH_SIZE and WRITE_SIZE (the first large copy of a counter run).
+    src = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
+    torch.empty_like(src).copy_(src)
+    torch.cuda.synchronize()
+    del src
     if args.workload.startswith("converge"):
         return bench_converge(args, specs[0])
     if args.workload.startswith("orbits"):
@@ -260,12 +266,6 @@ def main():
         plain = {"value": pts_step * Kp / tp, "unit": "pts/s", "steps": Kp,
                  "method": "loop_step per loop, sequential on one stream"}
 
-    # a plain device copy of known size: its counter readings calibrate FETCH_SIZE / WRITE_SIZE
-    src = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-
     cpu = None if args.no_cpu else cpu_baseline(specs, dtau, scheme)
     cpu_all = None if args.no_cpu else cpu_baseline_all_cores(specs, dtau, scheme)
 
@@ -321,10 +321,6 @@ def bench_resident(args, cfg, spec, steps, dtau, scheme):
     gpu_s = e0.elapsed_time(e1) * 1e-3
     fl = step_flops(spec.Nx, spec.Ns)
     achieved = fl * steps / gpu_s / 1e12
-    # a plain device copy of known size (counter calibration, as in the batched workloads)
-    src = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
-    torch.empty_like(src).copy_(src)
-    torch.cuda.synchronize()
     cpu = None if args.no_cpu else cpu_baseline([spec], dtau, scheme)
     out = {
         "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
@@ -475,10 +471,6 @@ def bench_xi(args, cfg, specs, steps, dtau, scheme):
     pts = Nx * Ns * nl
     by = xi_step_bytes(Nx, Ns) * nl
     achieved = by * steps / gpu_s / 1e9
-    # a plain device copy of known size (counter calibration, as in the batched workloads)
-    src = torch.empty(64 << 20, dtype=torch.uint8, device=dev)
-    torch.empty_like(src).copy_(src)
-    torch.cuda.synchronize()
     out = {
         "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
         "value": pts * steps / wall, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,

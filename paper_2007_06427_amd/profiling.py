@@ -104,15 +104,26 @@ def _per_kernel(counter_csv: str, counter: str):
     return acc
 
 
+def _calibration_copy(counter_csv: str, counter: str):
+    """The reading of the first copy dispatch among those with the largest grid of the run.
+
+    The device copy kernel's grid stops growing at a few megabytes, so copies of 64 MiB and
+    larger share one grid; bench.py makes its 64 MiB copy before any other large copy."""
+    rows = [r for r in csv.DictReader(open(counter_csv))
+            if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]]
+    if not rows:
+        return None
+    big = max(int(r["Grid_Size"]) for r in rows)
+    first = min((r for r in rows if int(r["Grid_Size"]) == big), key=lambda r: int(r["Dispatch_Id"]))
+    return float(first["Counter_Value"])
+
+
 def summarize_traffic(fetch_csv: str, write_csv: str, workload: str, command: str) -> None:
     fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
     write = _per_kernel(write_csv, "WRITE_SIZE")
-    # calibration: the largest device copy is the known 64 MiB one
-    copies = [(k, v) for k, v in fetch.items() if "copyBuffer" in k[0] or "elementwise" in k[0]]
+    # calibration: bench.py makes the known 64 MiB copy before any other copy of the run
     want_kib = COPY_BYTES / 1024
-    fcopy = max((max(v) for k, v in copies), default=None)
-    wcopies = [(k, v) for k, v in write.items() if "copyBuffer" in k[0] or "elementwise" in k[0]]
-    wcopy = max((max(v) for k, v in wcopies), default=None)
+    fcopy, wcopy = _calibration_copy(fetch_csv, "FETCH_SIZE"), _calibration_copy(write_csv, "WRITE_SIZE")
     ffac = (fcopy / want_kib) if fcopy else 1.0
     wfac = (wcopy / want_kib) if wcopy else 1.0
     # Per kernel, the launch over every loop of the plan (the largest grid), taken from
