@@ -7,10 +7,12 @@ are seeded synthetic loops, already resident in HBM when the timed region starts
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
 
 Workloads:
-  batched-ragged-256  (default) 256 loops, Nx in {32, 64}, Ns in {64..512}, L in {22, 39}, IMEX
-  batched-256x1024    64 loops of 256 x 1024, L = 100, IMEX
-  autograd-256x1024   the same 64 loops, G from the autograd path (LoopCost forward and its
-                      adjoint backward) and the update by loop_update
+  autograd-256x1024   (default) 64 loops of 256 x 1024, L = 100, IMEX dtau = 5e-5, 2000 steps:
+                      G from the autograd path (LoopCostBand forward and its adjoint backward)
+                      and one fused update kernel (loop_update_grad); beside it the same path on
+                      rfft-layout tensors, the fused batched step, the plain method and the oracle
+  batched-256x1024    the same 64 loops, fused batched step (loop_batch_step) alone
+  batched-ragged-256  256 loops, Nx in {32, 64}, Ns in {64..512}, L in {22, 39}, IMEX
   converge-32x32      the 32 x 32 loop driven to J < 1e-10 (IMEX, dtau = 0.05, J examined every
                       100 steps), with and without the extrapolations of App. C
   xi-256x1024         the same 64 loops projected onto centre-symmetric loops (u odd in x),
@@ -42,6 +44,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "space-time pts/s of r+J+adjoint G (FP64); batched vs plain; HBM GB/s fraction"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 CUS = 256
@@ -67,7 +70,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="batched-ragged-256", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="autograd-256x1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--runs", type=int, default=128, help="orbits-39: chaotic runs")
     ap.add_argument("--per-run", type=int, default=2, help="orbits-39: loops cut from each run")
@@ -270,7 +273,7 @@ def main():
     cpu_all = None if args.no_cpu else cpu_baseline_all_cores(specs, dtau, scheme)
 
     out = {
-        "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
+        "metric": METRIC,
         "value": value, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -323,7 +326,7 @@ def bench_resident(args, cfg, spec, steps, dtau, scheme):
     achieved = fl * steps / gpu_s / 1e12
     cpu = None if args.no_cpu else cpu_baseline([spec], dtau, scheme)
     out = {
-        "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
+        "metric": METRIC,
         "value": pts * steps / wall, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -342,23 +345,31 @@ def bench_resident(args, cfg, spec, steps, dtau, scheme):
     print(json.dumps(out))
 
 
-def autograd_bytes(Nx, Ns):
-    """Algorithmic HBM bytes of one autograd-path step of one loop (16 B per complex value;
-    R = Ns (Nx/2 + 1) values of the rfft-layout spectrum, S band values, W values of one
-    intermediate). Forward loop_cost: R + 3S + 4W (band conversion, passes A, B, C). Backward
-    loop_cost_grad: 2R + 7S + 9W (conversion, passes A-E, gradient out). G = -grad / (w_j L):
-    2R. loop_update: 3R."""
-    C = (Nx - 1) // 3 + 1
-    S = C * (2 * ((Ns - 1) // 3) + 1)
-    W = C * Ns
-    R = Ns * (Nx // 2 + 1)
-    return 16 * (8 * R + 10 * S + 13 * W)
+def autograd_kernel_bytes(Nx, Ns):
+    """Algorithmic HBM bytes of each kernel of one autograd-path step of one loop, band layout
+    (16 B per complex value; W = C Ns values of one transform intermediate, S = C NB band values):
+      forward  k_colA  reads u_hat, writes A                 S + W
+               k_rowB  reads A, writes B                     2W
+               k_colC  reads B and u_hat, writes r_hat       W + 2S
+      backward k_colAC reads u_hat and r_hat, writes A, C    2S + 2W
+               k_rowD  reads A and C, writes D               3W
+               k_colE  reads D and r_hat, writes the grad    W + 2S
+      update   k_update_grad_band reads u_hat, grad; writes u_hat   3S
+    16 (10W + 10S) per loop-step; the per-loop scalars (J, dJ/dT, T) are left out."""
+    W, S = band(Nx, Ns)
+    return {f"k_colA<{Ns}>": 16 * (S + W), f"k_rowB<{Nx}>": 16 * 2 * W, f"k_colC<{Ns}>": 16 * (W + 2 * S),
+            f"k_colAC<{Ns}>": 16 * (2 * S + 2 * W), f"k_rowD<{Nx}>": 16 * 3 * W, f"k_colE<{Ns}>": 16 * (W + 2 * S),
+            "k_update_grad_band": 16 * 3 * S}
 
 
 def bench_autograd(args, cfg, specs, steps, dtau, scheme):
-    """The large batched workload through the differentiable form: per step, J = LoopCost(u, T)
-    forward, J.sum().backward() (the hand-written adjoint kernel), G_1 = -grad / (w_j L) and
-    loop_update. The roofline is the whole step's algorithmic bytes over its time."""
+    """The large batched workload as specified: per step, J = LoopCostBand(u_hat, T) forward,
+    J.backward() through the hand-written adjoint kernel, and one fused update kernel
+    (loop_update_grad) that takes the gradient: G_1 = -grad / (w_j L), the IMEX step of u_hat and
+    the explicit step of T. The state is held in the band layout (the retained modes); the
+    conversion from and to the rfft layout is inside the timed region, once. Beside it: the same
+    path on rfft-layout tensors (LoopCost), the fused batched step (loop_batch_step, tuned) and
+    the plain method (loop_step per loop), all on the same loops, and the CPU oracle."""
     import numpy as np
     import torch
 
@@ -367,54 +378,149 @@ def bench_autograd(args, cfg, specs, steps, dtau, scheme):
     stream = torch.cuda.current_stream()
     L = specs[0].L
     Nx, Ns = specs[0].Nx, specs[0].Ns
+    nl = len(specs)
     assert all((s.L, s.Nx, s.Ns) == (L, Nx, Ns) for s in specs)
+    grid = (Nx, Ns)
     u0 = torch.from_numpy(np.stack([s.uhat for s in specs])).to(dev)
     T0 = torch.tensor([s.T for s in specs], dtype=torch.float64, device=dev)
-    w = torch.full((Nx // 2 + 1,), 2.0, dtype=torch.float64, device=dev)
-    w[0] = 1.0
-    winv = (-1.0 / (w * L)).to(torch.complex128)
+    ones = torch.ones(nl, dtype=torch.float64, device=dev)
+    ws = api.workspace(Nx, Ns, nl)
 
-    def run(u, T, k):
+    def run_band(ub, T, k):
+        for _ in range(k):
+            ua = ub.detach().requires_grad_(True)
+            Ta = T.detach().requires_grad_(True)
+            autograd.LoopCostBand.apply(ua, Ta, L, Nx, Ns).backward(ones)
+            api.loop_update_grad(ub, T, L, ua.grad, Ta.grad, dtau, scheme, layout=api.LAYOUT_BAND, grid=grid)
+
+    def run_rfft(u, T, k):
         for _ in range(k):
             ua = u.detach().requires_grad_(True)
             Ta = T.detach().requires_grad_(True)
-            autograd.LoopCost.apply(ua, Ta, L).sum().backward()
-            G = ua.grad.mul_(winv)
-            api.loop_update(u, T, L, G, Ta.grad, dtau, scheme)
+            autograd.LoopCost.apply(ua, Ta, L).backward(ones)
+            api.loop_update_grad(u, T, L, ua.grad, Ta.grad, dtau, scheme)
 
-    u, T = u0.clone(), T0.clone()
-    run(u, T, args.warmup)
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        out = fn(k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, e0.elapsed_time(e1) * 1e-3, out
+
+    def band_path(k):
+        ub, T = api.to_band(u0), T0.clone()
+        run_band(ub, T, k)
+        return api.from_band(ub, Nx, Ns), T
+
+    def rfft_path(k):
+        u, T = u0.clone(), T0.clone()
+        run_rfft(u, T, k)
+        return u, T
+
+    # ---- warm-up, then the timed region: K steps of the band-layout autograd path
+    band_path(args.warmup)
+    assert ws.status() == 0
+    wall, gpu_s, (u_ag, T_ag) = timed(band_path, steps)
+    assert ws.status() == 0, "device flagged a non-finite state"
+    J_end = api.loop_cost(u_ag, T_ag, L).cpu().numpy()
+    assert np.all(np.isfinite(J_end)) and bool(torch.all(T_ag > 0))
+    pts_step = Nx * Ns * nl
+    value = pts_step * steps / wall
+
+    # ---- per-kernel durations: HIP events around every launch on its stream, over a run of the
+    # same call sequence (kept apart from the timed region so that it runs undisturbed)
+    kb = autograd_kernel_bytes(Nx, Ns)
+    ktrace = min(steps, 50)
+    ub, T = api.to_band(u0), T0.clone()
+    run_band(ub, T, 2)
     torch.cuda.synchronize()
-    u, T = u0.clone(), T0.clone()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with api.trace() as tr:
+        run_band(ub, T, ktrace)
+    kern = {k: v for k, v in tr.kernels.items() if k in kb}
+    dom = max(kern, key=lambda k: kern[k]["total_us"])
+    by = kb[dom] * nl
+    achieved = by / (kern[dom]["avg_us"] * 1e-6) / 1e9
+    step_bytes = sum(kb.values()) * nl
+    traced_step_us = sum(v["total_us"] for v in tr.kernels.values()) / ktrace
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, dom),
+                "kernel": dom, "bytes_per_launch": by, "avg_launch_us": round(kern[dom]["avg_us"], 2),
+                "byte_model": "16 (10W + 10S) B per loop-step over seven kernels (W = C Ns, S = C NB)",
+                "kernels_us": {k: round(v["avg_us"], 2) for k, v in tr.kernels.items()},
+                "kernels_frac": {k: round(kb[k] * nl / (v["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+                                 for k, v in kern.items()},
+                "step_bytes": step_bytes,
+                "step_achieved": round(step_bytes / (gpu_s / steps) / 1e9, 1),
+                "step_frac": round(step_bytes / (gpu_s / steps) / 1e9 / HBM_PEAK_GBS, 4),
+                "traced_kernels_sum_vs_step": round(traced_step_us / (gpu_s / steps * 1e6), 3)}
+
+    # ---- the same path on rfft-layout tensors
+    k_r = min(steps, 200)
+    rfft_path(min(args.warmup, 5))
+    wall_r, gpu_r, (u_r, T_r) = timed(rfft_path, k_r)
+
+    # ---- the fused batched step on the same loops (tuned), K steps
+    batch = api.Batch([(s.L, s.Nx, s.Ns) for s in specs])
+    pool0 = batch.pack([torch.from_numpy(s.uhat) for s in specs])
+    tuning = batch.autotune(pool0, T0, reps=10)
+    pool, Tf = pool0.clone(), T0.clone()
+    batch.step(pool, Tf, dtau, scheme, args.warmup)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    run(u, T, steps)
-    e1.record(stream)
+
+    def fused(k):
+        pool, Tf = pool0.clone(), T0.clone()
+        batch.step(pool, Tf, dtau, scheme, k)
+        return pool, Tf
+    wall_f, gpu_f, (pool_f, T_f) = timed(fused, steps)
+    assert batch.status() == 0
+    u_f = torch.stack(batch.unpack(pool_f))
+    diff = float(np.max(np.abs(u_f.cpu().numpy() - u_ag.cpu().numpy())) / np.max(np.abs(u_f.cpu().numpy())))
+
+    # ---- plain method on the same loops: loop_step per loop, one after another
+    Kp = 10
+    sub = []
+    for s_ in specs:
+        u = torch.from_numpy(s_.uhat[None]).to(dev)
+        Tl = torch.tensor([s_.T], dtype=torch.float64, device=dev)
+        sub.append((u, Tl, api.Workspace(api.workspace_bytes(Nx, Ns, 1))))
+    for (u, Tl, w1) in sub:
+        api.loop_step(u, Tl, L, dtau, scheme, 1, ws=w1)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    J = api.loop_cost(u, T, L).cpu().numpy()
-    assert np.all(np.isfinite(J)) and torch.all(T > 0)
-    pts = Nx * Ns * len(specs)
-    by = autograd_bytes(Nx, Ns) * len(specs)
-    gpu_s = e0.elapsed_time(e1) * 1e-3
-    achieved = by * steps / gpu_s / 1e9
+    t1 = time.perf_counter()
+    for (u, Tl, w1) in sub:
+        api.loop_step(u, Tl, L, dtau, scheme, Kp, ws=w1)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t1
+    plain = {"value": pts_step * Kp / tp, "unit": "pts/s", "steps": Kp,
+             "method": "loop_step per loop, sequential on one stream"}
+
+    cpu = None if args.no_cpu else cpu_baseline(specs, dtau, scheme)
+    cpu_all = None if args.no_cpu else cpu_baseline_all_cores(specs, dtau, scheme)
     out = {
-        "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
-        "value": pts * steps / wall, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "metric": METRIC,
+        "value": value, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": args.workload, "loops": len(specs), "shapes": [[Nx, Ns]], "scheme": cfg["scheme"],
-                   "dtau": dtau, "form": "autograd G (LoopCost backward) + loop_update",
+        "config": {"workload": args.workload, "loops": nl, "shapes": [[Nx, Ns]], "L": L, "scheme": cfg["scheme"],
+                   "dtau": dtau, "form": "G from the autograd path (LoopCostBand forward + adjoint backward) "
+                                         "and the fused update loop_update_grad, band-layout state",
                    "parallelism": "none (1 GPU)"},
         "gpu_ms_per_step": gpu_s / steps * 1e3,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "whole autograd step (forward, adjoint backward, G, update)",
-                     "bytes_per_step": by},
-        "cpu_baseline": None,
-        "J_mean_end": float(J.mean()),
+        "roofline": roofline, "cpu_baseline": cpu, "cpu_baseline_all_cores": cpu_all,
+        "autograd_rfft_layout": {"value": pts_step * k_r / wall_r, "unit": "pts/s", "steps": k_r,
+                                 "gpu_ms_per_step": gpu_r / k_r * 1e3,
+                                 "method": "LoopCost on rfft-layout tensors + loop_update_grad"},
+        "fused": {"value": pts_step * steps / wall_f, "unit": "pts/s", "steps": steps,
+                  "gpu_ms_per_step": gpu_f / steps * 1e3, "schedule": tuning["schedule"],
+                  "variants": tuning["variants"], "method": "loop_batch_step (all steps in one call)"},
+        "autograd_vs_fused_time": round((gpu_s / steps) / (gpu_f / steps), 3),
+        "autograd_vs_fused_max_rel_diff": diff,
+        "plain": plain,
+        "batched_vs_plain": value / plain["value"],
+        "J_mean_end": float(J_end.mean()),
     }
     print(json.dumps(out))
 
@@ -472,7 +578,7 @@ def bench_xi(args, cfg, specs, steps, dtau, scheme):
     by = xi_step_bytes(Nx, Ns) * nl
     achieved = by * steps / gpu_s / 1e9
     out = {
-        "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
+        "metric": METRIC,
         "value": pts * steps / wall, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -541,7 +647,7 @@ def bench_expanded(args, cfg, specs, steps, dtau, scheme):
     by = expanded_step_bytes(Nx, Ns) * nl
     achieved = by * steps / gpu_s / 1e9
     out = {
-        "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
+        "metric": METRIC,
         "value": pts * steps / wall, "unit": "pts/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -581,7 +687,7 @@ def bench_converge(args, spec, dtau=0.05, J_tol=1e-10, stride=100):
     (rp, wp, Tp), (ra, wa, Ta) = runs[False], runs[True]
     pts = spec.Nx * spec.Ns
     out = {
-        "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
+        "metric": METRIC,
         "value": pts * ra["steps"][0] / wa, "unit": "pts/s", "n_gpus": 1, "steps": ra["steps"][0], "warmup": 0,
         "ms_per_step": wa / ra["steps"][0] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -662,7 +768,7 @@ def bench_orbits(args, E=128, per_run=2, chunk=400_000, J_tol=5e-25):
         f["repeat_of"] = base[0] if base else None
     pts = nl * 64 * 64
     out = {
-        "metric": "space-time pts/s of r+J+adjoint G+update (FP64)",
+        "metric": METRIC,
         "value": pts * done / t_conv, "unit": "pts/s", "n_gpus": 1, "steps": done, "warmup": 0,
         "ms_per_step": t_conv / done * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded chaotic KS runs)",

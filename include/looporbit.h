@@ -98,6 +98,48 @@ int loop_cost_grad(double L, int Nx, int Ns, int nloops, const double* T, const 
                    const double* gJ, double* grad_uhat, double* grad_T, void* ws, size_t ws_bytes,
                    void* stream);
 
+/* ---- Band layout and the reverse mode from a saved residual.
+ *
+ * Band layout: the retained coefficients alone, nloops x C x NB complex values with
+ * C = Kx + 1 and NB = 2 Ks + 1. Element [l][j][kk] holds u_hat_{j,k} of loop l for
+ * j = 0 .. Kx and kk = k (0 <= k <= Ks) or kk = k + NB (-Ks <= k < 0). As in the rfft layout,
+ * an entry with j >= 1 stands for itself and its partner (-j, -k), and column j = 0 holds
+ * both partners (k, -k) and is read through its Hermitian part. For the 256 x 1024 grid this
+ * is 0.44 of the rfft layout's size (the modes outside the band are always zero).
+ * loop_to_band / loop_from_band convert between the layouts (out of place; loop_to_band makes
+ * column 0 Hermitian, loop_from_band writes 0 outside the band).
+ *
+ * The cost of Sec. 3 as a forward and a reverse pass, for differentiation (eq. J_variation,
+ * eq. KS_L_dagger, App. B). The forward evaluates J = 1/2 int int r^2 and dJ/dT (each nloops,
+ * dJdT may be NULL) and leaves the residual r_hat in `rsave` (band layout, nloops x C x NB
+ * complex, caller-owned): the state-sized quantity the reverse pass needs. The reverse pass
+ * recomputes u on the grid from u_hat, forms r_x from the saved residual and applies the
+ * adjoint operator, G_1 = -(1/T) r_s - u r_x + r_xx + r_xxxx (eq. KS_G); none of the forward's
+ * transform intermediates is stored. It writes the gradient of sum_l gJ[l] J_l in the complex
+ * convention dJ/dRe + i dJ/dIm, in the layout of u:
+ *   grad_u = -gJ[l] w_j L G_1 in the band (w_0 = 1, w_j = 2 for j >= 1), 0 elsewhere,
+ *   grad_T[l] = gJ[l] dJdT[l] (dJdT from the forward; grad_T may be NULL),
+ * gJ may be NULL (all ones). The results equal loop_adjoint_grad's G_1 (scaled) bit for bit.
+ * `layout` is LOOP_LAYOUT_RFFT or LOOP_LAYOUT_BAND for u and grad_u. rsave must not alias u;
+ * grad_u must alias neither u nor rsave. Work space: loop_workspace_bytes. */
+typedef enum { LOOP_LAYOUT_RFFT = 0, LOOP_LAYOUT_BAND = 1 } loop_layout;
+int loop_to_band(int Nx, int Ns, int nloops, const double* uhat, double* uband, void* stream);
+int loop_from_band(int Nx, int Ns, int nloops, const double* uband, double* uhat, void* stream);
+int loop_cost_fwd(double L, int Nx, int Ns, int nloops, int layout, const double* T, const double* u,
+                  double* J, double* dJdT, double* rsave, void* ws, size_t ws_bytes, void* stream);
+int loop_cost_bwd(double L, int Nx, int Ns, int nloops, int layout, const double* T, const double* u,
+                  const double* rsave, const double* dJdT, const double* gJ, double* grad_u,
+                  double* grad_T, void* ws, size_t ws_bytes, void* stream);
+
+/* The fictitious-time update of Sec. 4.2 from the gradient of sum_l J_l (gJ = 1) in the
+ * convention above, in one kernel per array: G_1 = -grad_u / (w_j L) in the band, then
+ *   u <- canonical(u) + dtau * sigma_{j,k} * G_1,  sigma = 1 (EXPLICIT) or
+ *   1 / (1 - dtau lambda_{j,k}(T)) (IMEX), and T <- T - dtau * grad_T,
+ * with lambda and T as in loop_step (the period at the start of the step). `layout` as for
+ * loop_cost_bwd; in the rfft layout every entry outside the band is set to 0. */
+int loop_update_grad(double L, int Nx, int Ns, int nloops, int layout, double* T, double* u,
+                     const double* grad_u, const double* grad_T, double dtau, int scheme, void* stream);
+
 /* nsteps fictitious-time steps in place (Sec. 4.2):
  *   EXPLICIT: u_hat <- u_hat + dtau * G_1
  *   IMEX:     u_hat <- u_hat + dtau * G_1 / (1 - dtau * lambda_{j,k}(T)), the semi-implicit Euler
@@ -192,8 +234,9 @@ int loop_set_resident(int mode);
 int loop_resident_supported(int Nx, int Ns);
 int loop_step_form(int Nx, int Ns, int nloops);
 
-/* The update half of loop_step, for a G_1 computed elsewhere (e.g. by autograd):
- * uhat <- canonical(uhat) + dtau * sigma * Ghat (band), T <- T - dtau * dJdT[l]. */
+/* The update half of loop_step (the semi-implicit Euler step of Sec. 4.2), for a G_1 computed
+ * elsewhere: uhat <- canonical(uhat) + dtau * sigma * Ghat (band), T <- T - dtau * dJdT[l],
+ * with sigma as in loop_step. */
 int loop_update(double L, int Nx, int Ns, int nloops, double* T, double* uhat,
                 const double* Ghat, const double* dJdT, double dtau, int scheme, void* stream);
 
@@ -288,6 +331,20 @@ int loop_batch_set_variant(void* plan, int pass, int variant);
 int loop_batch_get_config(const void* plan, int* schedule, int* variants, int* nstreams);
 int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, int reps, double* report, void* ws,
                         size_t ws_bytes, void* stream);
+
+/* Kernel timing. Between loop_trace_start and loop_trace_stop, every pass kernel the library
+ * queues (and the conversions, finalize and update kernels) is bracketed by two HIP events
+ * recorded on the stream it is launched on. loop_trace_stop ends recording, waits for the
+ * recorded events and sums the durations per kernel; loop_trace_count and loop_trace_get
+ * then report, per kernel name (as in "k_rowD<256>" or "k_rag<3, 1>", in order of first
+ * launch): launches, total, shortest and longest duration in microseconds. Host calls that
+ * create events: not for use under stream capture. loop_trace_stop returns LOOP_EHIP if an
+ * event could not be created, recorded or read (the counts then cover the rest). */
+int loop_trace_start(void);
+int loop_trace_stop(void);
+int loop_trace_count(void);
+int loop_trace_get(int i, char* name, int name_len, long long* launches, double* total_us, double* min_us,
+                   double* max_us);
 
 /* Read (and clear) the sticky device status of a work space. Waits for `stream`. */
 int loop_status_sync(void* ws, void* stream);

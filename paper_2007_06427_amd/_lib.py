@@ -20,17 +20,21 @@ LOOP_EWORKSPACE = -5
 LOOP_EHANG = -6
 EXPLICIT = 0
 IMEX = 1
+LAYOUT_RFFT = 0
+LAYOUT_BAND = 1
 
 # every symbol include/looporbit.h and include/ks_initial_loops.h declare
 EXPORTS = [
     "loop_init", "loop_shutdown", "loop_workspace_bytes", "loop_workspace_init", "loop_residual",
-    "loop_cost", "loop_adjoint_grad", "loop_cost_grad", "loop_step", "loop_set_resident",
+    "loop_cost", "loop_adjoint_grad", "loop_cost_grad", "loop_to_band", "loop_from_band", "loop_cost_fwd",
+    "loop_cost_bwd", "loop_update_grad", "loop_step", "loop_set_resident",
     "loop_resident_supported", "loop_step_form", "loop_extrapolate", "loop_converge", "loop_step_xi",
     "loop_step_xi_workspace_bytes", "loop_expanded_grad", "loop_step_expanded", "loop_update", "loop_batch_create", "loop_batch_set_schedule", "loop_batch_set_streams",
     "loop_batch_destroy",
     "loop_batch_info", "loop_batch_workspace_init", "loop_batch_step", "loop_batch_load", "loop_batch_pass",
     "loop_batch_store", "loop_batch_set_variant", "loop_batch_get_config", "loop_batch_autotune",
-    "loop_status_sync", "loop_status_string",
+    "loop_status_sync", "loop_status_string", "loop_trace_start", "loop_trace_stop", "loop_trace_count",
+    "loop_trace_get",
     "ks_integrate", "ks_recurrences", "ks_segments_to_loops",
 ]
 
@@ -57,6 +61,11 @@ _SIGS = {
     "loop_cost": ([_d, _i, _i, _i, _p, _p, _p, _p, _sz, _p], _i),
     "loop_adjoint_grad": ([_d, _i, _i, _i, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
     "loop_cost_grad": ([_d, _i, _i, _i, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
+    "loop_to_band": ([_i, _i, _i, _p, _p, _p], _i),
+    "loop_from_band": ([_i, _i, _i, _p, _p, _p], _i),
+    "loop_cost_fwd": ([_d, _i, _i, _i, _i, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
+    "loop_cost_bwd": ([_d, _i, _i, _i, _i, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
+    "loop_update_grad": ([_d, _i, _i, _i, _i, _p, _p, _p, _p, _d, _i, _p], _i),
     "loop_step": ([_d, _i, _i, _i, _p, _p, _d, _i, _i, _p, _p, _sz, _p], _i),
     "loop_update": ([_d, _i, _i, _i, _p, _p, _p, _p, _d, _i, _p], _i),
     "loop_batch_create": ([_i, ctypes.POINTER(_d), ctypes.POINTER(_i), ctypes.POINTER(_i),
@@ -84,6 +93,11 @@ _SIGS = {
     "loop_batch_get_config": ([_p, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
     "loop_batch_autotune": ([_p, _p, _p, _i, ctypes.POINTER(_d), _p, _sz, _p], _i),
     "loop_status_sync": ([_p, _p], _i),
+    "loop_trace_start": ([], _i),
+    "loop_trace_stop": ([], _i),
+    "loop_trace_count": ([], _i),
+    "loop_trace_get": ([_i, ctypes.c_char_p, _i, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_d),
+                        ctypes.POINTER(_d), ctypes.POINTER(_d)], _i),
     "loop_status_string": ([_i], ctypes.c_char_p),
     "ks_integrate": ([_d, _i, _i, _i, _d, _i, _i, _p, _p, _p, _i, _p], _i),
     "ks_recurrences": ([_i, _i, _p, _i, _d, _d, _d, _d, _i, _p, _p, _p], _i),

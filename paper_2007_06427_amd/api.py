@@ -13,7 +13,7 @@ from typing import Dict, Tuple
 import torch
 
 from . import _lib
-from ._lib import EXPLICIT, IMEX, LoopOrbitError, check  # noqa: F401
+from ._lib import EXPLICIT, IMEX, LAYOUT_BAND, LAYOUT_RFFT, LoopOrbitError, check  # noqa: F401
 
 _WS: Dict[Tuple[int, int], "Workspace"] = {}
 
@@ -137,6 +137,90 @@ def loop_cost_grad(uhat: torch.Tensor, T, L: float, gJ: torch.Tensor = None, ws:
     check(_lib.lib().loop_cost_grad(float(L), Nx, Ns, nl, _ptr(T), _ptr(uhat), _ptr(gJ) if gJ is not None else None,
                                     _ptr(gu), _ptr(gT), ws.ptr, ws.nbytes, _stream_ptr()), "loop_cost_grad")
     return gu, gT
+
+
+def band_dims(Nx: int, Ns: int):
+    """(C, NB): retained spatial modes j = 0..Kx and temporal modes |k| <= Ks of the band layout."""
+    return (Nx - 1) // 3 + 1, 2 * ((Ns - 1) // 3) + 1
+
+
+def band_shape_of(ub: torch.Tensor, Nx: int, Ns: int) -> int:
+    """nloops of a band-layout tensor (nloops, C, NB) or (C, NB) for an Nx x Ns grid."""
+    C, NB = band_dims(Nx, Ns)
+    if ub.dtype != torch.complex128 or not ub.is_cuda or not ub.is_contiguous():
+        raise ValueError("band-layout state must be a contiguous complex128 device tensor")
+    if tuple(ub.shape[-2:]) != (C, NB) or ub.dim() not in (2, 3):
+        raise ValueError(f"band-layout state must be (nloops, {C}, {NB}) or ({C}, {NB}) for {Nx} x {Ns}")
+    return 1 if ub.dim() == 2 else int(ub.shape[0])
+
+
+def to_band(uhat: torch.Tensor) -> torch.Tensor:
+    """rfft layout -> band layout (nloops, C, NB), column 0 made Hermitian."""
+    nl, Nx, Ns = shape_of(uhat)
+    C, NB = band_dims(Nx, Ns)
+    ub = torch.empty((nl, C, NB) if uhat.dim() == 3 else (C, NB), dtype=torch.complex128, device=uhat.device)
+    check(_lib.lib().loop_to_band(Nx, Ns, nl, _ptr(uhat), _ptr(ub), _stream_ptr()), "loop_to_band")
+    return ub
+
+
+def from_band(ub: torch.Tensor, Nx: int, Ns: int) -> torch.Tensor:
+    """band layout -> rfft layout (zeros outside the band)."""
+    nl = band_shape_of(ub, Nx, Ns)
+    shape = (nl, Ns, Nx // 2 + 1) if ub.dim() == 3 else (Ns, Nx // 2 + 1)
+    uhat = torch.empty(shape, dtype=torch.complex128, device=ub.device)
+    check(_lib.lib().loop_from_band(Nx, Ns, nl, _ptr(ub), _ptr(uhat), _stream_ptr()), "loop_from_band")
+    return uhat
+
+
+def _layout_of(u: torch.Tensor, layout: int, grid):
+    if layout == LAYOUT_RFFT:
+        return shape_of(u)
+    Nx, Ns = grid
+    return band_shape_of(u, Nx, Ns), int(Nx), int(Ns)
+
+
+def loop_cost_fwd(u: torch.Tensor, T, L: float, layout: int = LAYOUT_RFFT, grid=None, ws: Workspace = None):
+    """Forward pass of the cost: (J, dJ/dT, rsave), rsave the band residual the reverse pass
+    takes. `grid` = (Nx, Ns) for the band layout."""
+    nl, Nx, Ns = _layout_of(u, layout, grid)
+    T = _periods(T, nl, u.device)
+    C, NB = band_dims(Nx, Ns)
+    J = torch.empty(nl, dtype=torch.float64, device=u.device)
+    dJdT = torch.empty(nl, dtype=torch.float64, device=u.device)
+    rsave = torch.empty((nl, C, NB), dtype=torch.complex128, device=u.device)
+    ws = ws or workspace(Nx, Ns, nl)
+    check(_lib.lib().loop_cost_fwd(float(L), Nx, Ns, nl, int(layout), _ptr(T), _ptr(u), _ptr(J), _ptr(dJdT),
+                                   _ptr(rsave), ws.ptr, ws.nbytes, _stream_ptr()), "loop_cost_fwd")
+    return J, dJdT, rsave
+
+
+def loop_cost_bwd(u: torch.Tensor, T, L: float, rsave: torch.Tensor, dJdT: torch.Tensor, gJ: torch.Tensor = None,
+                  layout: int = LAYOUT_RFFT, grid=None, ws: Workspace = None):
+    """Reverse pass from the forward's saved residual: (grad_u, grad_T) of sum_l gJ[l] J_l."""
+    nl, Nx, Ns = _layout_of(u, layout, grid)
+    T = _periods(T, nl, u.device)
+    if gJ is not None and (gJ.dtype != torch.float64 or gJ.numel() != nl or not gJ.is_contiguous()):
+        raise ValueError("gJ must be a contiguous float64 tensor with one entry per loop")
+    gu = torch.empty_like(u)
+    gT = torch.empty(nl, dtype=torch.float64, device=u.device)
+    ws = ws or workspace(Nx, Ns, nl)
+    check(_lib.lib().loop_cost_bwd(float(L), Nx, Ns, nl, int(layout), _ptr(T), _ptr(u), _ptr(rsave), _ptr(dJdT),
+                                   _ptr(gJ) if gJ is not None else None, _ptr(gu), _ptr(gT), ws.ptr, ws.nbytes,
+                                   _stream_ptr()), "loop_cost_bwd")
+    return gu, gT
+
+
+def loop_update_grad(u: torch.Tensor, T: torch.Tensor, L: float, grad_u: torch.Tensor, grad_T: torch.Tensor,
+                     dtau: float, scheme: int = EXPLICIT, layout: int = LAYOUT_RFFT, grid=None):
+    """In place: the step of Sec. 4.2 from the gradient of sum_l J_l (G_1 = -grad_u / (w_j L))."""
+    nl, Nx, Ns = _layout_of(u, layout, grid)
+    T = _periods(T, nl, u.device)
+    if grad_u.shape != u.shape or grad_u.dtype != u.dtype or not grad_u.is_contiguous():
+        raise ValueError("grad_u must match u")
+    grad_T = _periods(grad_T, nl, u.device)
+    check(_lib.lib().loop_update_grad(float(L), Nx, Ns, nl, int(layout), _ptr(T), _ptr(u), _ptr(grad_u), _ptr(grad_T),
+                                      float(dtau), int(scheme), _stream_ptr()), "loop_update_grad")
+    return u, T
 
 
 def loop_step(uhat: torch.Tensor, T: torch.Tensor, L: float, dtau: float, scheme: int = EXPLICIT,
@@ -410,3 +494,30 @@ class Batch:
                 self._plan = None
         except Exception:
             pass
+
+
+class trace:
+    """Kernel timing by HIP events around each library launch (see loop_trace_start):
+
+        with api.trace() as tr:
+            ...                       # library calls
+        tr.kernels                    # {name: {"launches", "total_us", "avg_us", "min_us", "max_us"}}
+    """
+
+    def __enter__(self):
+        check(_lib.lib().loop_trace_start(), "loop_trace_start")
+        self.kernels = {}
+        return self
+
+    def __exit__(self, *exc):
+        check(_lib.lib().loop_trace_stop(), "loop_trace_stop")
+        L = _lib.lib()
+        buf = ctypes.create_string_buffer(128)
+        n, tot, lo, hi = ctypes.c_longlong(0), ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+        for i in range(L.loop_trace_count()):
+            check(L.loop_trace_get(i, buf, 128, ctypes.byref(n), ctypes.byref(tot), ctypes.byref(lo), ctypes.byref(hi)),
+                  "loop_trace_get")
+            self.kernels[buf.value.decode()] = {"launches": int(n.value), "total_us": tot.value,
+                                                "avg_us": tot.value / max(n.value, 1), "min_us": lo.value,
+                                                "max_us": hi.value}
+        return False

@@ -9,6 +9,7 @@
 #include <atomic>
 #include <cstring>
 #include <map>
+#include <string>
 #include <mutex>
 #include <type_traits>
 #include <vector>
@@ -54,9 +55,15 @@ __global__ __launch_bounds__(kBlock) void k_rowD(Shape sh, Work w, double* T, in
 
 template <int N>
 __global__ __launch_bounds__(kBlock) void k_colE(Shape sh, Work w, int mode, double dtau, int scheme, int fuseA,
-                                                 const cd* __restrict__ tw) {
+                                                 const cd* __restrict__ tw, const double* __restrict__ T) {
     __shared__ cd ex[ColG<N>::LDS];
-    col_pass_E<N>(sh, blockIdx.x, w, mode, dtau, scheme, fuseA != 0, ex, tw);
+    col_pass_E<N>(sh, blockIdx.x, w, mode, dtau, scheme, fuseA != 0, ex, tw, T);
+}
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_colAC(Shape sh, Work w, const cd* __restrict__ tw) {
+    __shared__ cd ex[ColG<N>::LDS];
+    col_pass_AC<N>(sh, blockIdx.x, w, ex, tw);
 }
 
 // one wavefront per loop
@@ -291,6 +298,82 @@ __global__ void k_update(Shape sh, const double* __restrict__ T, cd* uhat, const
     }
 }
 
+// The update from a gradient in torch's convention (the gradient of sum_l J_l): G_1 = -grad /
+// (w_j L), then as k_update. rfft layout.
+__global__ void k_update_grad(Shape sh, const double* __restrict__ T, cd* uhat, const cd* __restrict__ grad,
+                              double dtau, int scheme) {
+    const size_t per = (size_t)sh.N * sh.H;
+    const size_t total = per * sh.nloops;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t l = i / per;
+        const int e = (int)((i % per) / sh.H), j = (int)(i % sh.H);
+        if (j == 0 && e > sh.N / 2) continue;  // handled with its partner row
+        cd* u = uhat + l * per;
+        const cd* g = grad + l * per;
+        const bool inb = band_row(e, sh.N, sh.Ks) >= 0 && j < sh.C;
+        const int e2 = (sh.N - e) & (sh.N - 1);
+        if (!inb) {
+            u[(size_t)e * sh.H + j] = cd{0.0, 0.0};
+            if (j == 0) u[(size_t)e2 * sh.H] = cd{0.0, 0.0};
+            continue;
+        }
+        cd uu = u[(size_t)e * sh.H + j], gg = g[(size_t)e * sh.H + j];
+        if (j == 0) {
+            const cd pu = u[(size_t)e2 * sh.H], pg = g[(size_t)e2 * sh.H];
+            uu = cd{0.5 * (uu.x + pu.x), 0.5 * (uu.y - pu.y)};
+            gg = cd{0.5 * (gg.x + pg.x), 0.5 * (gg.y - pg.y)};
+        }
+        const double f = -1.0 / ((j == 0 ? 1.0 : 2.0) * sh.L);  // G_1 = -grad / (w_j L)
+        gg = cd{f * gg.x, f * gg.y};
+        double sig = 1.0;
+        if (scheme == 1) {
+            const int k = (e < sh.N / 2) ? e : e - sh.N;
+            const double q = kTwoPi * j / sh.L, q2 = q * q, q4 = q2 * q2;
+            const double a = kTwoPi * k / T[l];
+            sig = 1.0 / (1.0 - dtau * (-q4 * q4 + 2.0 * q4 * q2 - q4 - a * a));
+        }
+        const double s = dtau * sig;
+        const cd v{uu.x + s * gg.x, uu.y + s * gg.y};
+        u[(size_t)e * sh.H + j] = v;
+        if (j == 0) u[(size_t)e2 * sh.H] = cconj(v);
+    }
+}
+
+// The same update on band-layout state and gradient ([l][j][kk]); column 0 is read through its
+// Hermitian part and written Hermitian (one thread per pair k, -k).
+__global__ void k_update_grad_band(Shape sh, const double* __restrict__ T, cd* ub, const cd* __restrict__ grad,
+                                   double dtau, int scheme) {
+    const size_t per = (size_t)sh.C * sh.NB;
+    const size_t total = per * sh.nloops;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t l = i / per;
+        const int j = (int)((i % per) / sh.NB), kk = (int)(i % sh.NB);
+        if (j == 0 && kk > sh.Ks) continue;  // handled with its partner
+        cd* u = ub + l * per + (size_t)j * sh.NB;
+        const cd* g = grad + l * per + (size_t)j * sh.NB;
+        const int kp = band_partner(kk, sh.NB);
+        cd uu = u[kk], gg = g[kk];
+        if (j == 0) {
+            const cd pu = u[kp], pg = g[kp];
+            uu = cd{0.5 * (uu.x + pu.x), 0.5 * (uu.y - pu.y)};
+            gg = cd{0.5 * (gg.x + pg.x), 0.5 * (gg.y - pg.y)};
+        }
+        const double f = -1.0 / ((j == 0 ? 1.0 : 2.0) * sh.L);
+        gg = cd{f * gg.x, f * gg.y};
+        double sig = 1.0;
+        if (scheme == 1) {
+            const int k = (kk <= sh.Ks) ? kk : kk - sh.NB;
+            const double q = kTwoPi * j / sh.L, q2 = q * q, q4 = q2 * q2;
+            const double a = kTwoPi * k / T[l];
+            sig = 1.0 / (1.0 - dtau * (-q4 * q4 + 2.0 * q4 * q2 - q4 - a * a));
+        }
+        const double s = dtau * sig;
+        const cd v{uu.x + s * gg.x, uu.y + s * gg.y};
+        u[kk] = v;
+        if (j == 0 && kk != 0) u[kp] = cconj(v);
+    }
+}
+
 __global__ void k_update_T(int nloops, double* T, const double* __restrict__ dJdT, double dtau) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l < nloops) T[l] = T[l] - dtau * dJdT[l];
@@ -388,7 +471,7 @@ struct BatchArgs {
 constexpr uint64_t kSpinTicks = 200000000ull;  // 2 s of the 100 MHz constant clock
 
 __device__ __forceinline__ Work batch_work(const BatchLoop& b, char* ws, int* status) {
-    Work w;
+    Work w{};
     w.A = reinterpret_cast<cd*>(ws + b.off.A);
     w.BD = reinterpret_cast<cd*>(ws + b.off.BD);
     w.Cb = reinterpret_cast<cd*>(ws + b.off.Cb);
@@ -647,7 +730,7 @@ __global__ __launch_bounds__(kBlock, (ResG<M, N>::BLOCKS_PER_CU)) void k_residen
     const int l = blockIdx.x;
     Shape s1 = sh;
     s1.nloops = 1;
-    Work w;
+    Work w{};
     w.A = A;
     w.BD = X;
     w.Cb = X;
@@ -902,6 +985,66 @@ int prepare(double L, int Nx, int Ns, int nloops, void* ws, size_t ws_bytes, Sha
     return get_table(tw);
 }
 
+// ---------------------------------------------------------------------------- kernel timing
+// While tracing is on (loop_trace_start), each traced launch is bracketed by two HIP events
+// recorded on the launch's own stream; loop_trace_stop reads them and sums the durations per
+// kernel. Off (the default), a TraceScope costs one relaxed atomic load.
+std::atomic<int> g_trace_on{0};
+struct TraceRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+struct TraceStat {
+    long long launches = 0;
+    double total_us = 0.0, min_us = 1e300, max_us = 0.0;
+};
+std::mutex g_trace_mu;
+std::vector<TraceRec> g_trace_recs;
+std::vector<hipEvent_t> g_trace_pool;
+std::vector<std::pair<std::string, TraceStat>> g_trace_stats;
+bool g_trace_failed = false;
+
+hipEvent_t trace_event() {
+    if (!g_trace_pool.empty()) {
+        hipEvent_t e = g_trace_pool.back();
+        g_trace_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct TraceScope {
+    hipEvent_t a = nullptr;
+    hipStream_t st = nullptr;
+    std::string name;
+    TraceScope(const char* base, int size, hipStream_t s) : TraceScope(base, size, 0, s) {}
+    TraceScope(const char* base, int size, int size2, hipStream_t s) {
+        if (!g_trace_on.load(std::memory_order_relaxed)) return;
+        std::lock_guard<std::mutex> g(g_trace_mu);
+        a = trace_event();
+        if (!a || hipEventRecord(a, s) != hipSuccess) {
+            g_trace_failed = true;
+            a = nullptr;
+            return;
+        }
+        st = s;
+        name = std::string(base);
+        if (size > 0) name += "<" + std::to_string(size) + (size2 > 0 ? ", " + std::to_string(size2) : "") + ">";
+    }
+    ~TraceScope() {
+        if (!a) return;
+        std::lock_guard<std::mutex> g(g_trace_mu);
+        hipEvent_t b = trace_event();
+        if (!b || hipEventRecord(b, st) != hipSuccess) {
+            g_trace_failed = true;
+            return;
+        }
+        g_trace_recs.push_back(TraceRec{name, a, b});
+    }
+};
+
 // ---------------------------------------------------------------------------- launchers
 #define LO_SWITCH_SIZE(n, BODY)                     \
     switch (n) {                                    \
@@ -937,37 +1080,49 @@ unsigned row_blocks(const Shape& s) {
 }
 
 int launch_A(const Shape& s, const Work& w, const cd* tw, hipStream_t st) {
-    LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_colA<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
+    LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colA", S_, st);
+                   hipLaunchKernelGGL(k_colA<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
     return LOOP_OK;
 }
 int launch_B(const Shape& s, const Work& w, const cd* tw, hipStream_t st) {
-    LO_SWITCH_SIZE(s.M, hipLaunchKernelGGL(k_rowB<S_>, dim3(row_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
+    LO_SWITCH_SIZE(s.M, TraceScope ts_("k_rowB", S_, st);
+                   hipLaunchKernelGGL(k_rowB<S_>, dim3(row_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
     return LOOP_OK;
 }
 int launch_C(const Shape& s, const double* T, const Work& w, int mode, double dtau, int scheme, const cd* tw,
              hipStream_t st) {
-    LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_colC<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, T, w, mode,
+    LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colC", S_, st);
+                   hipLaunchKernelGGL(k_colC<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, T, w, mode,
                                            dtau, scheme, tw));
     return LOOP_OK;
 }
 int launch_D(const Shape& s, const Work& w, double* T, int mode, double dtau, double* J_hist, double* Jout,
              double* dJdTout, const cd* tw, hipStream_t st) {
-    LO_SWITCH_SIZE(s.M, hipLaunchKernelGGL(k_rowD<S_>, dim3(row_blocks(s)), dim3(kBlock), 0, st, s, w, T, mode,
+    LO_SWITCH_SIZE(s.M, TraceScope ts_("k_rowD", S_, st);
+                   hipLaunchKernelGGL(k_rowD<S_>, dim3(row_blocks(s)), dim3(kBlock), 0, st, s, w, T, mode,
                                            dtau, J_hist, Jout, dJdTout, tw));
     return LOOP_OK;
 }
 int launch_E(const Shape& s, const Work& w, int mode, double dtau, int scheme, int fuseA, const cd* tw,
-             hipStream_t st) {
-    LO_SWITCH_SIZE(s.N, hipLaunchKernelGGL(k_colE<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, mode, dtau,
-                                           scheme, fuseA, tw));
+             hipStream_t st, const double* T = nullptr) {
+    LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colE", S_, st);
+                   hipLaunchKernelGGL(k_colE<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, mode, dtau,
+                                           scheme, fuseA, tw, T));
+    return LOOP_OK;
+}
+int launch_AC(const Shape& s, const Work& w, const cd* tw, hipStream_t st) {
+    LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colAC", S_, st);
+                   hipLaunchKernelGGL(k_colAC<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
     return LOOP_OK;
 }
 void launch_to_band(const Shape& s, const cd* uhat, cd* U, hipStream_t st) {
     dim3 grid((s.NB + 31) / 32, (s.C + 31) / 32, s.nloops);
+    TraceScope ts_("k_to_band", 0, st);
     hipLaunchKernelGGL(k_to_band, grid, dim3(256), 0, st, s, uhat, U);
 }
 void launch_from_band(const Shape& s, const cd* src, cd* out, hipStream_t st) {
     dim3 grid((s.N + 31) / 32, (s.H + 31) / 32, s.nloops);
+    TraceScope ts_("k_from_band", 0, st);
     hipLaunchKernelGGL(k_from_band, grid, dim3(256), 0, st, s, src, out);
 }
 
@@ -1147,6 +1302,7 @@ int launch_resident(const Shape& s, cd* u, double* T, double dtau, int scheme, i
             if constexpr (R::FITS) {
                 auto k = k_resident<M_, N_>;
                 if ((st = ensure_lds_limit(reinterpret_cast<const void*>(k), R::BYTES))) return;
+                TraceScope ts_("k_resident", M_, N_, hs);
                 hipLaunchKernelGGL(k, dim3(s.nloops), dim3(kBlock), R::BYTES, hs, s, u, u, T, dtau, scheme, nsteps,
                                    J_hist, status, tw);
                 st = last_error();
@@ -1261,6 +1417,35 @@ unsigned elem_blocks(size_t n) {
 
 }  // namespace
 
+namespace {
+// Argument checks of the stepping entry points.
+int step_args(const double* T, const double* uhat, double dtau, int scheme, int nsteps, const double* J_hist) {
+    if (!aligned(T, 8) || !aligned(uhat, 16) || (J_hist && !aligned(J_hist, 8))) return LOOP_EINVAL;
+    if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1) || nsteps < 0) return LOOP_EINVAL;
+    return LOOP_OK;
+}
+
+// The steps of loop_step on a prepared work space: the resident form, or the per-pass kernels
+// between the conversions into and out of the band layout.
+int step_impl(const Shape& s, const Work& w, const cd* tw, double* T, cd* u, double dtau, int scheme, int nsteps,
+              double* J_hist, hipStream_t hs) {
+    int st;
+    if (loop_step_form(s.M, s.N, s.nloops) == 1)
+        return launch_resident(s, u, T, dtau, scheme, nsteps, J_hist, w.status, tw, hs);
+    launch_to_band(s, u, w.U, hs);
+    if (nsteps > 0 && (st = launch_A(s, w, tw, hs))) return st;
+    for (int i = 0; i < nsteps; ++i) {
+        double* jh = J_hist ? J_hist + (size_t)i * s.nloops : nullptr;
+        if ((st = launch_B(s, w, tw, hs))) return st;
+        if ((st = launch_C(s, T, w, MODE_STEP, dtau, scheme, tw, hs))) return st;
+        if ((st = launch_D(s, w, T, MODE_STEP, dtau, jh, nullptr, nullptr, tw, hs))) return st;
+        if ((st = launch_E(s, w, MODE_STEP, dtau, scheme, i + 1 < nsteps, tw, hs))) return st;
+    }
+    launch_from_band(s, w.U, u, hs);
+    return last_error();
+}
+}  // namespace
+
 // ============================================================================ C ABI
 // Configurations chosen by loop_batch_autotune, per device and multiset of (Nx, Ns), for
 // the plans created later in the process.
@@ -1322,7 +1507,7 @@ int loop_workspace_init(void* ws, size_t ws_bytes, void* stream) {
 int loop_residual(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat, double* rhat,
                   void* ws, size_t ws_bytes, void* stream) {
     Shape s;
-    Work w;
+    Work w{};
     const cd* tw;
     if (!aligned(T, 8) || !aligned(uhat, 16) || !aligned(rhat, 16) || (const void*)uhat == (const void*)rhat)
         return LOOP_EINVAL;
@@ -1340,7 +1525,7 @@ int loop_residual(double L, int Nx, int Ns, int nloops, const double* T, const d
 int loop_cost(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat, double* J, void* ws,
               size_t ws_bytes, void* stream) {
     Shape s;
-    Work w;
+    Work w{};
     const cd* tw;
     if (!aligned(T, 8) || !aligned(uhat, 16) || !aligned(J, 8)) return LOOP_EINVAL;
     int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
@@ -1358,7 +1543,7 @@ int loop_cost(double L, int Nx, int Ns, int nloops, const double* T, const doubl
 int loop_adjoint_grad(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat, double* Ghat,
                       double* dJdT, double* J, void* ws, size_t ws_bytes, void* stream) {
     Shape s;
-    Work w;
+    Work w{};
     const cd* tw;
     if (!aligned(T, 8) || !aligned(uhat, 16) || !aligned(Ghat, 16) || (const void*)uhat == (const void*)Ghat)
         return LOOP_EINVAL;
@@ -1379,7 +1564,7 @@ int loop_adjoint_grad(double L, int Nx, int Ns, int nloops, const double* T, con
 int loop_cost_grad(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat, const double* gJ,
                    double* grad_uhat, double* grad_T, void* ws, size_t ws_bytes, void* stream) {
     Shape s;
-    Work w;
+    Work w{};
     const cd* tw;
     if (!aligned(T, 8) || !aligned(uhat, 16) || !aligned(grad_uhat, 16) || !aligned(grad_T, 8) ||
         (gJ && !aligned(gJ, 8)) || (const void*)uhat == (const void*)grad_uhat)
@@ -1399,36 +1584,138 @@ int loop_cost_grad(double L, int Nx, int Ns, int nloops, const double* T, const 
     return last_error();
 }
 
-int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau, int scheme, int nsteps,
-              double* J_hist, void* ws, size_t ws_bytes, void* stream) {
+int loop_to_band(int Nx, int Ns, int nloops, const double* uhat, double* uband, void* stream) {
+    int st = check_shape(1.0, Nx, Ns, nloops);
+    if (st) return st;
+    if (!aligned(uhat, 16) || !aligned(uband, 16) || (const void*)uhat == (const void*)uband) return LOOP_EINVAL;
+    launch_to_band(make_shape(1.0, Nx, Ns, nloops), reinterpret_cast<const cd*>(uhat), reinterpret_cast<cd*>(uband),
+                   (hipStream_t)stream);
+    return last_error();
+}
+
+int loop_from_band(int Nx, int Ns, int nloops, const double* uband, double* uhat, void* stream) {
+    int st = check_shape(1.0, Nx, Ns, nloops);
+    if (st) return st;
+    if (!aligned(uhat, 16) || !aligned(uband, 16) || (const void*)uhat == (const void*)uband) return LOOP_EINVAL;
+    launch_from_band(make_shape(1.0, Nx, Ns, nloops), reinterpret_cast<const cd*>(uband), reinterpret_cast<cd*>(uhat),
+                     (hipStream_t)stream);
+    return last_error();
+}
+
+namespace {
+// The field state of a reverse-mode call: rfft layout converted into the work space's band
+// array (canonical), or a caller-owned band array read in place (column 0 through its
+// Hermitian part).
+int bind_state(const Shape& s, Work& w, int layout, const double* u, hipStream_t hs) {
+    if (layout == LOOP_LAYOUT_RFFT) {
+        launch_to_band(s, reinterpret_cast<const cd*>(u), w.U, hs);
+        w.herm0 = 0;
+    } else if (layout == LOOP_LAYOUT_BAND) {
+        w.U = const_cast<cd*>(reinterpret_cast<const cd*>(u));
+        w.herm0 = 1;
+    } else {
+        return LOOP_EINVAL;
+    }
+    return LOOP_OK;
+}
+}  // namespace
+
+int loop_cost_fwd(double L, int Nx, int Ns, int nloops, int layout, const double* T, const double* u, double* J,
+                  double* dJdT, double* rsave, void* ws, size_t ws_bytes, void* stream) {
     Shape s;
     Work w;
     const cd* tw;
-    if (!aligned(T, 8) || !aligned(uhat, 16) || (J_hist && !aligned(J_hist, 8))) return LOOP_EINVAL;
-    if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1) || nsteps < 0) return LOOP_EINVAL;
+    if (layout != LOOP_LAYOUT_RFFT && layout != LOOP_LAYOUT_BAND) return LOOP_EINVAL;
+    if (!aligned(T, 8) || !aligned(u, 16) || !aligned(J, 8) || !aligned(rsave, 16) || (dJdT && !aligned(dJdT, 8)) ||
+        (const void*)u == (const void*)rsave)
+        return LOOP_EINVAL;
     int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
     if (st) return st;
     hipStream_t hs = (hipStream_t)stream;
-    cd* u = reinterpret_cast<cd*>(uhat);
-    if (loop_step_form(Nx, Ns, nloops) == 1)
-        return launch_resident(s, u, T, dtau, scheme, nsteps, J_hist, w.status, tw, hs);
-    launch_to_band(s, u, w.U, hs);
-    if (nsteps > 0 && (st = launch_A(s, w, tw, hs))) return st;
-    for (int i = 0; i < nsteps; ++i) {
-        double* jh = J_hist ? J_hist + (size_t)i * nloops : nullptr;
-        if ((st = launch_B(s, w, tw, hs))) return st;
-        if ((st = launch_C(s, T, w, MODE_STEP, dtau, scheme, tw, hs))) return st;
-        if ((st = launch_D(s, w, T, MODE_STEP, dtau, jh, nullptr, nullptr, tw, hs))) return st;
-        if ((st = launch_E(s, w, MODE_STEP, dtau, scheme, i + 1 < nsteps, tw, hs))) return st;
+    if ((st = bind_state(s, w, layout, u, hs))) return st;
+    w.G = reinterpret_cast<cd*>(rsave);  // pass C writes the residual there
+    if ((st = launch_A(s, w, tw, hs))) return st;
+    if ((st = launch_B(s, w, tw, hs))) return st;
+    if ((st = launch_C(s, T, w, MODE_RESIDUAL, 0.0, 0, tw, hs))) return st;
+    {
+        TraceScope ts_("k_finalize", 0, hs);
+        hipLaunchKernelGGL(k_finalize, dim3(nloops), dim3(64), 0, hs, s, w, const_cast<double*>(T), J, dJdT);
     }
-    launch_from_band(s, w.U, u, hs);
     return last_error();
+}
+
+int loop_cost_bwd(double L, int Nx, int Ns, int nloops, int layout, const double* T, const double* u,
+                  const double* rsave, const double* dJdT, const double* gJ, double* grad_u, double* grad_T, void* ws,
+                  size_t ws_bytes, void* stream) {
+    Shape s;
+    Work w;
+    const cd* tw;
+    if (layout != LOOP_LAYOUT_RFFT && layout != LOOP_LAYOUT_BAND) return LOOP_EINVAL;
+    if (!aligned(T, 8) || !aligned(u, 16) || !aligned(rsave, 16) || !aligned(grad_u, 16) || (gJ && !aligned(gJ, 8)) ||
+        (const void*)grad_u == (const void*)u || (const void*)grad_u == (const void*)rsave)
+        return LOOP_EINVAL;
+    if (grad_T && (!aligned(grad_T, 8) || !aligned(dJdT, 8))) return LOOP_EINVAL;
+    int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
+    if (st) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    if ((st = bind_state(s, w, layout, u, hs))) return st;
+    w.R = reinterpret_cast<const cd*>(rsave);
+    w.gJ = gJ;
+    cd* gout = w.G;  // band result in the work space, converted below (rfft layout)
+    if (layout == LOOP_LAYOUT_BAND) w.G = reinterpret_cast<cd*>(grad_u);
+    if ((st = launch_AC(s, w, tw, hs))) return st;
+    if ((st = launch_D(s, w, const_cast<double*>(T), MODE_ADJOINT, 0.0, nullptr, nullptr, nullptr, tw, hs))) return st;
+    if ((st = launch_E(s, w, MODE_ADJOINT, 0.0, 0, 0, tw, hs, T))) return st;
+    if (layout == LOOP_LAYOUT_RFFT) launch_from_band(s, gout, reinterpret_cast<cd*>(grad_u), hs);
+    if (grad_T) {
+        TraceScope ts_("k_grad_T", 0, hs);
+        hipLaunchKernelGGL(k_grad_T, dim3((nloops + 255) / 256), dim3(256), 0, hs, nloops, gJ, dJdT, grad_T);
+    }
+    return last_error();
+}
+
+int loop_update_grad(double L, int Nx, int Ns, int nloops, int layout, double* T, double* u, const double* grad_u,
+                     const double* grad_T, double dtau, int scheme, void* stream) {
+    int st = check_shape(L, Nx, Ns, nloops);
+    if (st) return st;
+    if (layout != LOOP_LAYOUT_RFFT && layout != LOOP_LAYOUT_BAND) return LOOP_EINVAL;
+    if (!aligned(T, 8) || !aligned(u, 16) || !aligned(grad_u, 16) || !aligned(grad_T, 8) ||
+        (const void*)u == (const void*)grad_u)
+        return LOOP_EINVAL;
+    if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1)) return LOOP_EINVAL;
+    const Shape s = make_shape(L, Nx, Ns, nloops);
+    hipStream_t hs = (hipStream_t)stream;
+    if (layout == LOOP_LAYOUT_RFFT) {
+        TraceScope ts_("k_update_grad", 0, hs);
+        hipLaunchKernelGGL(k_update_grad, dim3(elem_blocks((size_t)s.nloops * s.N * s.H)), dim3(256), 0, hs, s, T,
+                           reinterpret_cast<cd*>(u), reinterpret_cast<const cd*>(grad_u), dtau, scheme);
+    } else {
+        TraceScope ts_("k_update_grad_band", 0, hs);
+        hipLaunchKernelGGL(k_update_grad_band, dim3(elem_blocks((size_t)s.nloops * s.C * s.NB)), dim3(256), 0, hs, s,
+                           T, reinterpret_cast<cd*>(u), reinterpret_cast<const cd*>(grad_u), dtau, scheme);
+    }
+    {
+        TraceScope ts_("k_update_T", 0, hs);
+        hipLaunchKernelGGL(k_update_T, dim3((nloops + 255) / 256), dim3(256), 0, hs, nloops, T, grad_T, dtau);
+    }
+    return last_error();
+}
+
+int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau, int scheme, int nsteps,
+              double* J_hist, void* ws, size_t ws_bytes, void* stream) {
+    Shape s;
+    Work w{};
+    const cd* tw;
+    int st = step_args(T, uhat, dtau, scheme, nsteps, J_hist);
+    if (st) return st;
+    if ((st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw))) return st;
+    return step_impl(s, w, tw, T, reinterpret_cast<cd*>(uhat), dtau, scheme, nsteps, J_hist, (hipStream_t)stream);
 }
 
 int loop_expanded_grad(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat, double* Ghat,
                        double* dJdT, double* J, void* ws, size_t ws_bytes, void* stream) {
     Shape s;
-    Work w;
+    Work w{};
     const cd* tw;
     if (!aligned(T, 8) || !aligned(uhat, 16) || !aligned(Ghat, 16) || (const void*)uhat == (const void*)Ghat)
         return LOOP_EINVAL;
@@ -1447,7 +1734,7 @@ int loop_expanded_grad(double L, int Nx, int Ns, int nloops, const double* T, co
 int loop_step_expanded(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau, int scheme,
                        int nsteps, double* J_hist, void* ws, size_t ws_bytes, void* stream) {
     Shape s;
-    Work w;
+    Work w{};
     const cd* tw;
     if (!aligned(T, 8) || !aligned(uhat, 16) || (J_hist && !aligned(J_hist, 8))) return LOOP_EINVAL;
     if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1) || nsteps < 0) return LOOP_EINVAL;
@@ -1684,7 +1971,7 @@ int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns,
     for (int l = 0; l < nloops; ++l) {
         BatchLoop& b = p->loops[l];
         b.sh = make_shape(L[l], Nx[l], Ns[l], 1);
-        Work w;
+        Work w{};
         const size_t sz = layout(b.sh, reinterpret_cast<char*>(off), &w);
         const size_t base = off;
         auto rel = [&](const void* q) { return (size_t)reinterpret_cast<uintptr_t>(q); };
@@ -1870,12 +2157,23 @@ BatchArgs batch_args(const BatchPlan* p, char* base, double* T, double* J_hist, 
 }
 
 // One pass over the tiles c[0 .. n) with the plan's variant for that pass.
+const char* rag_name(int pass, int v) {
+    static const char* names[5][kRagVariants] = {
+        {"k_rag<0, 0>", "k_rag<0, 1>", "k_rag<0, 2>", "k_rag<0, 3>"},
+        {"k_rag<1, 0>", "k_rag<1, 1>", "k_rag<1, 2>", "k_rag<1, 3>"},
+        {"k_rag<2, 0>", "k_rag<2, 1>", "k_rag<2, 2>", "k_rag<2, 3>"},
+        {"k_rag<3, 0>", "k_rag<3, 1>", "k_rag<3, 2>", "k_rag<3, 3>"},
+        {"k_rag<4, 0>", "k_rag<4, 1>", "k_rag<4, 2>", "k_rag<4, 3>"}};
+    return names[pass][v];
+}
+
 void launch_pass_codes(const BatchPlan* p, int pass, int step, const BatchArgs& a, hipStream_t hs,
                        const uint32_t* c, int n) {
     if (n == 0) return;
     const dim3 grid(n);
     const int v = p->variant[pass];
     const size_t lds = p->pass_lds[pass][v];
+    TraceScope ts_(rag_name(pass, v), 0, hs);
     switch (pass) {
         case PASS_A: launch_rag<PASS_A>(v, grid, lds, hs, a, c, step); break;
         case PASS_B: launch_rag<PASS_B>(v, grid, lds, hs, a, c, step); break;
@@ -1933,6 +2231,7 @@ int loop_batch_load(const void* plan, const double* uhat_pool, void* ws, size_t 
     int st = batch_check(p, ws, ws_bytes, &tw);
     if (st) return st;
     if (!aligned(uhat_pool, 16)) return LOOP_EINVAL;
+    TraceScope ts_("k_to_band_batch", 0, (hipStream_t)stream);
     hipLaunchKernelGGL(k_to_band_batch, dim3((p->max_nb + 31) / 32, (p->max_c + 31) / 32, p->nloops), dim3(256), 0,
                        (hipStream_t)stream, p->d_loops, reinterpret_cast<const cd*>(uhat_pool), static_cast<char*>(ws));
     return last_error();
@@ -1944,6 +2243,7 @@ int loop_batch_store(const void* plan, double* uhat_pool, void* ws, size_t ws_by
     int st = batch_check(p, ws, ws_bytes, &tw);
     if (st) return st;
     if (!aligned(uhat_pool, 16)) return LOOP_EINVAL;
+    TraceScope ts_("k_from_band_batch", 0, (hipStream_t)stream);
     hipLaunchKernelGGL(k_from_band_batch, dim3((p->max_n + 31) / 32, (p->max_h + 31) / 32, p->nloops), dim3(256), 0,
                        (hipStream_t)stream, p->d_loops, static_cast<const char*>(ws), reinterpret_cast<cd*>(uhat_pool));
     return last_error();
@@ -1980,6 +2280,7 @@ int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau,
         if (p->schedule == LOOP_BATCH_PERSISTENT) {
             const long long total = (long long)p->nA + (long long)nsteps * p->ips;
             if (total >= (1ll << 31)) return LOOP_EINVAL;
+            TraceScope ts_("k_batch", 0, hs);
             hipLaunchKernelGGL(k_batch, dim3(p->grid), dim3(kBlock), p->lds_bytes, hs, a);
         } else if (p->schedule == LOOP_BATCH_STREAMS) {
             if ((st = launch_streams(p, nsteps, a, hs))) return st;
@@ -2126,6 +2427,66 @@ int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, in
     for (int pass = PASS_A; pass <= PASS_E; ++pass) c.variant[pass] = p->variant[pass];
     std::lock_guard<std::mutex> g(g_tune_mu);
     tune_cache()[plan_signature(p)] = c;
+    return LOOP_OK;
+}
+
+int loop_trace_start(void) {
+    std::lock_guard<std::mutex> g(g_trace_mu);
+    for (auto& r : g_trace_recs) {
+        g_trace_pool.push_back(r.a);
+        g_trace_pool.push_back(r.b);
+    }
+    g_trace_recs.clear();
+    g_trace_stats.clear();
+    g_trace_failed = false;
+    g_trace_on.store(1);
+    return LOOP_OK;
+}
+
+int loop_trace_stop(void) {
+    g_trace_on.store(0);
+    std::lock_guard<std::mutex> g(g_trace_mu);
+    std::map<std::string, TraceStat> acc;
+    std::vector<std::string> order;
+    bool ok = !g_trace_failed;
+    for (auto& r : g_trace_recs) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+            ok = false;
+        } else {
+            if (!acc.count(r.name)) order.push_back(r.name);
+            TraceStat& t = acc[r.name];
+            const double us = 1e3 * (double)ms;
+            t.launches += 1;
+            t.total_us += us;
+            t.min_us = std::min(t.min_us, us);
+            t.max_us = std::max(t.max_us, us);
+        }
+        g_trace_pool.push_back(r.a);
+        g_trace_pool.push_back(r.b);
+    }
+    g_trace_recs.clear();
+    g_trace_stats.clear();
+    for (const auto& n : order) g_trace_stats.emplace_back(n, acc[n]);
+    return ok ? LOOP_OK : LOOP_EHIP;
+}
+
+int loop_trace_count(void) {
+    std::lock_guard<std::mutex> g(g_trace_mu);
+    return (int)g_trace_stats.size();
+}
+
+int loop_trace_get(int i, char* name, int name_len, long long* launches, double* total_us, double* min_us,
+                   double* max_us) {
+    std::lock_guard<std::mutex> g(g_trace_mu);
+    if (i < 0 || i >= (int)g_trace_stats.size() || !name || name_len < 1) return LOOP_EINVAL;
+    const auto& e = g_trace_stats[i];
+    std::strncpy(name, e.first.c_str(), (size_t)name_len - 1);
+    name[name_len - 1] = 0;
+    if (launches) *launches = e.second.launches;
+    if (total_us) *total_us = e.second.total_us;
+    if (min_us) *min_us = e.second.min_us;
+    if (max_us) *max_us = e.second.max_us;
     return LOOP_OK;
 }
 

@@ -49,6 +49,8 @@ enum Mode : int {
     MODE_COST = 1,      // pass C partials only
     MODE_GRAD = 2,      // pass C writes G_lin, pass E turns it into G_1
     MODE_STEP = 3,      // pass C writes U1, pass D advances T, pass E writes u_hat'
+    MODE_ADJOINT = 4,   // reverse mode from a saved residual: pass D skips the finalize, pass E
+                        // forms G_lin from R and writes scale_l w_j G_1 into G
 };
 
 struct Shape {
@@ -73,7 +75,24 @@ struct Work {
     double* dJdT;     // [l]
     double* Told;     // [l]  period at the start of the current step
     int* status;      // sticky device status
+    const cd* R;      // [l][j][kk] saved residual r_hat (MODE_ADJOINT)
+    const double* gJ;  // [l] cotangent of J (MODE_ADJOINT; null: all ones)
+    int herm0;        // U is caller-owned: read column 0 through its Hermitian part
 };
+
+// Band index of the temporal partner -k of band index kk (k -> -k).
+__device__ __forceinline__ int band_partner(int kk, int NB) { return kk == 0 ? 0 : NB - kk; }
+
+// Band value u[kk] of column j; with herm0, column 0 is read through its Hermitian part
+// (u_{0,k} + conj u_{0,-k}) / 2, the part a real field keeps.
+__device__ __forceinline__ cd band_get(const cd* u, int j, int kk, int NB, int herm0) {
+    const cd v = u[kk];
+    if (herm0 && j == 0) {
+        const cd w = u[band_partner(kk, NB)];
+        return cd{0.5 * (v.x + w.x), 0.5 * (v.y - w.y)};
+    }
+    return v;
+}
 
 constexpr double kTwoPi = 6.283185307179586476925286766559005768;
 
@@ -167,9 +186,42 @@ __device__ __forceinline__ void col_pass_A(const Shape& sh, int block, const Wor
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) {
         const int kk = band_row(p.t + m * G::TPF, N, sh.Ks);
-        v[m] = (p.active && kk >= 0) ? u[kk] : cd{0.0, 0.0};
+        v[m] = (p.active && kk >= 0) ? band_get(u, p.j, kk, sh.NB, w.herm0) : cd{0.0, 0.0};
     }
     col_inverse_store<N>(sh, p, v, w.A, ex, twc);
+}
+
+// Reverse mode, first pass: the inverse s-transforms of u_hat (into A, as pass A) and of
+// i q r_hat from the saved residual (into C, as pass C would leave it), column by column.
+template <int N>
+__device__ __forceinline__ void col_pass_AC(const Shape& sh, int block, const Work& w, cd* ex,
+                                            const cd* __restrict__ tw) {
+    using G = ColG<N>;
+    const ColPos p = col_pos<N>(sh, block);
+    TwCache<N, G::PT> twc;
+    tw_cache_load<N, G::PT>(twc, p.t, tw);
+    const size_t col = (size_t)p.l * sh.C + p.j;
+    const cd* u = w.U + col * sh.NB;
+    const cd* r = w.R + col * sh.NB;
+    const double q = kTwoPi * p.j / sh.L;
+    cd v[G::PT];
+#pragma unroll
+    for (int m = 0; m < G::PT; ++m) {
+        const int kk = band_row(p.t + m * G::TPF, N, sh.Ks);
+        v[m] = (p.active && kk >= 0) ? band_get(u, p.j, kk, sh.NB, w.herm0) : cd{0.0, 0.0};
+    }
+    col_inverse_store<N>(sh, p, v, w.A, ex, twc);
+#pragma unroll
+    for (int m = 0; m < G::PT; ++m) {
+        const int kk = band_row(p.t + m * G::TPF, N, sh.Ks);
+        cd x{0.0, 0.0};
+        if (p.active && kk >= 0) {
+            const cd rr = r[kk];
+            x = cd{-q * rr.y, q * rr.x};  // i q r
+        }
+        v[m] = x;
+    }
+    col_inverse_store<N>(sh, p, v, w.Cb, ex, twc);
 }
 
 template <int N>
@@ -206,7 +258,7 @@ __device__ __forceinline__ void col_pass_C(const Shape& sh, int block, const dou
             const int k = (e < N / 2) ? e : e - N;
             const double om = kTwoPi * k;
             const cd wh = cscale(v[m], invN);  // (u u_x)_hat
-            const cd uu = u[kk];
+            const cd uu = band_get(u, p.j, kk, sh.NB, w.herm0);
             const double a = om * invT;
             // r = -(i om/T) u - (u u_x)_hat + (q^2 - q^4) u
             cd r;
@@ -242,7 +294,8 @@ __device__ __forceinline__ void col_pass_C(const Shape& sh, int block, const dou
 
 template <int N>
 __device__ __forceinline__ void col_pass_E(const Shape& sh, int block, const Work& w, int mode, double dtau,
-                                           int scheme, bool fuseA, cd* ex, const cd* __restrict__ tw) {
+                                           int scheme, bool fuseA, cd* ex, const cd* __restrict__ tw,
+                                           const double* __restrict__ T = nullptr) {
     using G = ColG<N>;
     const ColPos p = col_pos<N>(sh, block);
     const size_t col = (size_t)p.l * sh.C + p.j;
@@ -258,9 +311,14 @@ __device__ __forceinline__ void col_pass_E(const Shape& sh, int block, const Wor
     const double q = kTwoPi * p.j / sh.L;
     const double q2 = q * q, q4 = q2 * q2;
     const double lamx = -q4 * q4 + 2.0 * q4 * q2 - q4;
-    const double Tl = (mode == MODE_STEP && p.active) ? w.Told[p.l] : 1.0;
+    const double Tl = (mode == MODE_STEP && p.active) ? w.Told[p.l] : (mode == MODE_ADJOINT && p.active) ? T[p.l] : 1.0;
+    // reverse mode: G_1 scaled by -gJ_l w_j L, the gradient of sum_l gJ_l J_l in torch's
+    // complex convention (gJ folded in by the caller as scale_l = -gJ_l L)
+    const double sc = (mode == MODE_ADJOINT && p.active) ? (w.gJ ? -w.gJ[p.l] : -1.0) * sh.L * (p.j == 0 ? 1.0 : 2.0)
+                                                         : 1.0;
     cd* g = w.G + col * sh.NB;
     cd* u = w.U + col * sh.NB;
+    const cd* r = w.R + col * sh.NB;
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) {
         const int e = p.t + m * G::TPF;
@@ -268,6 +326,19 @@ __device__ __forceinline__ void col_pass_E(const Shape& sh, int block, const Wor
         cd x{0.0, 0.0};
         if (p.active && kk >= 0) {
             const cd ph = cscale(v[m], invN);  // (u r_x)_hat
+            if (mode == MODE_ADJOINT) {
+                // G_lin = (-i om/T - q^2 + q^4) r, as pass C forms it, then G_1 = G_lin - p_hat
+                const cd rr = r[kk];
+                const int k = (e < N / 2) ? e : e - N;
+                const double a = kTwoPi * k * (1.0 / Tl);
+                cd gl;
+                gl.x = a * rr.y + (q4 - q2) * rr.x;
+                gl.y = -a * rr.x + (q4 - q2) * rr.y;
+                const cd g1 = csub(gl, ph);
+                g[kk] = cd{sc * g1.x, sc * g1.y};
+                v[m] = x;
+                continue;
+            }
             const cd gg = g[kk];
             if (mode == MODE_STEP) {
                 double sig = 1.0;
@@ -557,7 +628,7 @@ __device__ __forceinline__ void row_pass_D(const Shape& sh, int block, const Wor
     // Loops whose first row lies in this block are finished here (partials from pass C), by
     // wavefront 0 while the first sub-tile's loads are in flight.
     auto finalize = [&]() {
-        if (threadIdx.x < 64) {
+        if (mode != MODE_ADJOINT && threadIdx.x < 64) {
             const size_t l0 = (gb + sh.N - 1) >> sh.logN;  // first loop starting at or after gb
             for (size_t l = l0; (l << sh.logN) < gb + RowG<M>::ROWS && l < (size_t)sh.nloops; ++l)
                 finalize_loop(sh, (int)l, w, T, mode, dtau, J_hist, Jout, dJdTout);

@@ -396,7 +396,7 @@ __device__ __forceinline__ void xi_row_pass_D(const Shape& sh, int block, const 
     if (threadIdx.x < 64) {
         Shape sx = sh;
         sx.C = sh.Kx;  // one partial pair per column j = 1..Kx
-        Work wf;
+        Work wf{};
         wf.partial = w.partial;
         wf.J = w.J;
         wf.dJdT = w.dJdT;

@@ -132,7 +132,7 @@ def summarize_traffic(fetch_csv: str, write_csv: str, workload: str, command: st
     kernels = {}
     for key in sorted(set(fetch) & set(write), key=lambda k: (k[0], -int(k[1]))):
         name = key[0]
-        if not name.startswith("k_rag") and name != "k_batch":
+        if not name.startswith("k_"):
             continue
         if name in kernels:
             continue
@@ -173,7 +173,7 @@ def summarize_counters(p1_csv: str, p2_csv: str, workload: str, command: str) ->
     a, b = load(p1_csv), load(p2_csv)
     best = {}
     for (k, g) in set(a) & set(b):
-        if k.startswith("k_rag") and (k not in best or g > best[k]):
+        if k.startswith("k_") and (k not in best or g > best[k]):
             best[k] = g
     lines = [f"# SQ counters per dispatch: {workload}", "",
              f"Two counter runs of: `{command}`, the first with `--pmc SQ_WAVE_CYCLES SQ_BUSY_CYCLES "

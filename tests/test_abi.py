@@ -92,6 +92,39 @@ def test_entry_points_reject_bad_arguments_on_host():
     assert L.loop_status_sync(odd, None) == _lib.LOOP_EINVAL
 
 
+def test_reverse_mode_entry_points_reject_bad_arguments_on_host():
+    L = _lib.lib()
+    fake, fake2, fake3 = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21), ctypes.c_void_p(1 << 22)
+    odd = ctypes.c_void_p((1 << 20) + 8)
+    ws = ctypes.c_void_p(1 << 24)
+    E, W = _lib.LOOP_EINVAL, _lib.LOOP_EWORKSPACE
+    band, rfft = _lib.LAYOUT_BAND, _lib.LAYOUT_RFFT
+    fwd = L.loop_cost_fwd
+    assert fwd(22.0, 32, 32, 1, 7, fake, fake, fake2, None, fake3, ws, 1 << 30, None) == E  # layout
+    assert fwd(22.0, 32, 32, 1, rfft, fake, odd, fake2, None, fake3, ws, 1 << 30, None) == E  # misaligned u
+    assert fwd(22.0, 32, 32, 1, band, fake, fake3, fake2, None, fake3, ws, 1 << 30, None) == E  # rsave aliases u
+    assert fwd(22.0, 32, 32, 1, band, fake, fake, fake2, None, fake3, ws, 1024, None) == W
+    bwd = L.loop_cost_bwd
+    assert bwd(22.0, 32, 32, 1, rfft, fake, fake, fake2, fake, None, fake, None, ws, 1 << 30, None) == E  # grad = u
+    assert bwd(22.0, 32, 32, 1, rfft, fake, fake, fake2, fake, None, fake2, None, ws, 1 << 30, None) == E  # = rsave
+    bad8 = ctypes.c_void_p((1 << 20) + 4)
+    assert bwd(22.0, 32, 32, 1, band, fake, fake, fake2, bad8, None, fake3, fake, ws, 1 << 30, None) == E  # dJdT
+    upd = L.loop_update_grad
+    assert upd(22.0, 32, 32, 1, band, fake, fake2, fake2, fake, 1e-4, 1, None) == E  # grad aliases u
+    assert upd(22.0, 32, 32, 1, band, fake, fake2, fake3, fake, 0.0, 1, None) == E  # dtau
+    assert upd(22.0, 32, 32, 1, 3, fake, fake2, fake3, fake, 1e-4, 1, None) == E  # layout
+    assert L.loop_to_band(32, 32, 1, fake, fake, None) == E
+    assert L.loop_from_band(48, 32, 1, fake, fake2, None) == _lib.LOOP_ENOTSUP
+
+
+def test_trace_outside_a_session_reports_nothing():
+    L = _lib.lib()
+    assert L.loop_trace_start() == 0 and L.loop_trace_stop() == 0
+    assert L.loop_trace_count() == 0
+    buf = ctypes.create_string_buffer(16)
+    assert L.loop_trace_get(0, buf, 16, None, None, None, None) == _lib.LOOP_EINVAL
+
+
 def test_initial_loop_entry_points_reject_bad_arguments_on_host():
     L = _lib.lib()
     fake = ctypes.c_void_p(1 << 20)

@@ -71,3 +71,11 @@ def test_flop_model_counts_every_transform():
     transforms = 4 * C * 5 * Ns * np.log2(Ns) + 2 * (Ns // 2) * 3 * 5 * Nx * np.log2(Nx)
     pointwise = bench.step_flops(Nx, Ns) - transforms
     assert 0 < pointwise < 0.2 * bench.step_flops(Nx, Ns)
+
+
+def test_autograd_kernels_add_up_to_their_step_model():
+    """The seven kernels of an autograd-path step move 16 (10W + 10S) bytes per loop."""
+    for Nx, Ns in [(64, 256), (256, 1024)]:
+        W, S = bench.band(Nx, Ns)
+        kb = bench.autograd_kernel_bytes(Nx, Ns)
+        assert len(kb) == 7 and sum(kb.values()) == 16 * (10 * W + 10 * S)

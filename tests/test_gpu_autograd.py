@@ -1,11 +1,13 @@
 """GPU tests of the differentiable form: J(u_hat, T) as a torch.autograd.Function whose
-backward is the hand-written adjoint kernel (loop_cost_grad).
+backward is the hand-written adjoint kernel (loop_cost_fwd / loop_cost_bwd).
 
 Checks: forward against the oracle's J; backward against the oracle's gradient (which
 test_oracle.py pins against torch's own autograd through torch.fft); central finite
 differences of the GPU forward in 32 random unit directions of (u_hat, T) at h = 1e-6 (the
-64 x 256, L = 39 differentiation workload); torch.autograd.gradcheck on a small grid; and
-that the Function saves only its inputs, so intermediates are recomputed, not stored.
+64 x 256, L = 39 differentiation workload); torch.autograd.gradcheck on a small grid; that the
+Function saves its inputs and the band residual only (the transform intermediates are
+recomputed, not stored); the band-layout form against the rfft-layout one; and the step from
+the gradient (loop_update_grad) against the fused step.
 """
 import numpy as np
 import pytest
@@ -96,34 +98,119 @@ def test_gradcheck_small_grid(ag):
 
 
 def test_backward_recomputes_instead_of_storing(ag):
+    """The context holds the inputs, the band residual (C x NB per loop, smaller than the input)
+    and dJ/dT: no grid-sized transform intermediate (C x Ns or more per loop)."""
     spec = loopgen.config_loops(3)[0]
     u = torch.from_numpy(spec.uhat[None]).to(DEV).requires_grad_(True)
     T = torch.tensor([spec.T], dtype=torch.float64, device=DEV, requires_grad=True)
     J = ag.LoopCost.apply(u, T, spec.L)
     saved = J.grad_fn.saved_tensors
-    assert len(saved) == 2 and saved[0].shape == u.shape and saved[1].shape == T.shape
+    C, NB = (spec.Nx - 1) // 3 + 1, 2 * ((spec.Ns - 1) // 3) + 1
+    assert len(saved) == 4 and saved[0].shape == u.shape and saved[1].shape == T.shape
+    assert tuple(saved[2].shape) == (1, C, NB) and tuple(saved[3].shape) == (1,)
+    assert all(t.numel() < C * spec.Ns for t in saved[1:])
 
 
-def test_autograd_step_equals_fused_step(ag):
-    """The large batched workload's autograd path: G from the backward plus loop_update equals
-    the fused loop_step (checked on 4 loops of 256 x 1024)."""
+def test_reverse_pass_equals_adjoint_grad_bitwise(ag):
+    """loop_cost_fwd + loop_cost_bwd give loop_cost's J and -gJ w_j L G_1 of loop_adjoint_grad
+    exactly (the same kernels' arithmetic, the residual handed over in HBM)."""
+    from paper_2007_06427_amd import api
+    specs = loopgen.config_loops(5, 2) + [loopgen.random_loop(77, 22.0, 256, 1024, 40, 100, 0.5, 0.05, 40.0)]
+    L = 100.0
+    u = torch.from_numpy(np.stack([s.uhat for s in specs])).to(DEV)
+    T = torch.tensor([s.T for s in specs], dtype=torch.float64, device=DEV)
+    J, dJdT, rs = api.loop_cost_fwd(u, T, L)
+    gJ = torch.tensor([1.0, -0.25, 3.0], dtype=torch.float64, device=DEV)
+    gu, gT = api.loop_cost_bwd(u, T, L, rs, dJdT, gJ)
+    G, dT2, J2 = api.loop_adjoint_grad(u, T, L)
+    gu2, gT2 = api.loop_cost_grad(u, T, L, gJ)
+    assert torch.equal(J, J2) and torch.equal(dJdT, dT2)
+    assert torch.equal(gu, gu2) and torch.equal(gT, gT2)
+    w = torch.full((u.shape[-1],), 2.0, dtype=torch.float64, device=DEV)
+    w[0] = 1.0
+    assert torch.equal(gu[0], -(1.0 * L) * w * G[0])
+
+
+def test_band_layout_matches_rfft_layout(ag):
+    """LoopCostBand on loop_to_band's output gives J, the gradient (converted) and dJ/dT of
+    LoopCost bit for bit; a non-Hermitian column 0 is read through its Hermitian part."""
+    from paper_2007_06427_amd import api
+    specs = loopgen.config_loops(3) + [loopgen.random_loop(3002, 39.0, 64, 256, 8, 8, 0.5, 0.2, (30.0, 60.0))]
+    L, Nx, Ns = specs[0].L, specs[0].Nx, specs[0].Ns
+    u = torch.from_numpy(np.stack([s.uhat for s in specs])).to(DEV)
+    T0 = torch.tensor([s.T for s in specs], dtype=torch.float64, device=DEV)
+    ua = u.clone().requires_grad_(True)
+    Ta = T0.clone().requires_grad_(True)
+    Ja = ag.LoopCost.apply(ua, Ta, L)
+    Ja.sum().backward()
+    ub = api.to_band(u)
+    assert torch.equal(api.from_band(ub, Nx, Ns), torch.from_numpy(np.stack([K.canonical(s.uhat) for s in specs])).to(DEV))
+    ubr = ub.clone().requires_grad_(True)
+    Tb = T0.clone().requires_grad_(True)
+    Jb = ag.LoopCostBand.apply(ubr, Tb, L, Nx, Ns)
+    Jb.sum().backward()
+    assert torch.equal(Ja, Jb) and torch.equal(Ta.grad, Tb.grad)
+    # the raw gradients agree exactly (to_band of the rfft one would average column 0's partners,
+    # which the kernels leave Hermitian only to rounding)
+    assert torch.equal(api.from_band(ubr.grad, Nx, Ns), ua.grad)
+    # an anti-Hermitian addition to column 0 changes neither J nor the gradient
+    rng = np.random.default_rng(4)
+    bump = torch.from_numpy(rng.standard_normal(ub.shape[-1]) + 1j * rng.standard_normal(ub.shape[-1])).to(DEV)
+    NB = ub.shape[-1]
+    anti = bump - torch.conj(bump[(NB - torch.arange(NB, device=DEV)) % NB])
+    ubx = ub.clone()
+    ubx[:, 0, :] += anti
+    Jx, dTx, _ = api.loop_cost_fwd(ubx, T0, L, layout=api.LAYOUT_BAND, grid=(Nx, Ns))
+    assert torch.allclose(Jx, Jb.detach(), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("layout", ["rfft", "band"])
+def test_autograd_step_equals_fused_step(ag, layout):
+    """The large batched workload's autograd path: the gradient from the backward and one
+    loop_update_grad kernel per array equal the fused loop_step (4 loops of 256 x 1024)."""
     from paper_2007_06427_amd import api
     specs = loopgen.config_loops(5, 4)
-    L = specs[0].L
+    L, Nx, Ns = specs[0].L, specs[0].Nx, specs[0].Ns
     u = torch.from_numpy(np.stack([s.uhat for s in specs])).to(DEV)
     T = torch.tensor([s.T for s in specs], dtype=torch.float64, device=DEV)
     u2, T2 = u.clone(), T.clone()
+    x = api.to_band(u) if layout == "band" else u
     for _ in range(2):
-        ua = u.clone().requires_grad_(True)
-        Ta = T.clone().requires_grad_(True)
-        ag.LoopCost.apply(ua, Ta, L).sum().backward()
-        # G_1 = -grad / (w_j L); dJ/dT = grad_T
-        w = torch.full((u.shape[-1],), 2.0, dtype=torch.float64, device=DEV)
-        w[0] = 1.0
-        G = -ua.grad / (w * L)
-        api.loop_update(u, T, L, G.contiguous(), Ta.grad.contiguous(), 5e-5, api.IMEX)
+        xa = x.detach().requires_grad_(True)
+        Ta = T.detach().requires_grad_(True)
+        if layout == "band":
+            ag.LoopCostBand.apply(xa, Ta, L, Nx, Ns).sum().backward()
+            api.loop_update_grad(x, T, L, xa.grad, Ta.grad, 5e-5, api.IMEX, layout=api.LAYOUT_BAND, grid=(Nx, Ns))
+        else:
+            ag.LoopCost.apply(xa, Ta, L).sum().backward()
+            api.loop_update_grad(x, T, L, xa.grad, Ta.grad, 5e-5, api.IMEX)
+    if layout == "band":
+        x = api.from_band(x, Nx, Ns)
     api.loop_step(u2, T2, L, 5e-5, api.IMEX, 2)
-    a, b = u.cpu().numpy(), u2.cpu().numpy()
+    a, b = x.cpu().numpy(), u2.cpu().numpy()
     for i in range(len(specs)):
         assert wrel(a[i], b[i]) < 1e-13
     assert torch.allclose(T, T2, rtol=1e-14, atol=0)
+
+
+def test_update_grad_equals_loop_update(ag):
+    """loop_update_grad(grad) equals loop_update(G_1 = -grad / (w_j L)) formed on the host."""
+    from paper_2007_06427_amd import api
+    spec = loopgen.config_loops(3)[0]
+    L = spec.L
+    u = torch.from_numpy(spec.uhat[None]).to(DEV)
+    T = torch.tensor([spec.T], dtype=torch.float64, device=DEV)
+    rng = np.random.default_rng(9)
+    g = torch.from_numpy(loopgen.random_band_field(rng, spec.Nx, spec.Ns)[None]).to(DEV)
+    gT = torch.tensor([0.3], dtype=torch.float64, device=DEV)
+    w = torch.full((u.shape[-1],), 2.0, dtype=torch.float64, device=DEV)
+    w[0] = 1.0
+    for scheme in (api.EXPLICIT, api.IMEX):
+        u1, T1 = u.clone(), T.clone()
+        u2, T2 = u.clone(), T.clone()
+        api.loop_update_grad(u1, T1, L, g, gT, 1e-4, scheme)
+        api.loop_update(u2, T2, L, (g * (-1.0 / (w * L))).contiguous(), gT, 1e-4, scheme)
+        assert wrel(u1[0].cpu().numpy(), u2[0].cpu().numpy()) < 1e-15
+        assert torch.equal(T1, T2)
+
+
