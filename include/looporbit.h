@@ -150,6 +150,25 @@ int loop_update_grad(double L, int Nx, int Ns, int nloops, int layout, double* T
 int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau,
               int scheme, int nsteps, double* J_hist, void* ws, size_t ws_bytes, void* stream);
 
+/* loop_step for callers that cannot allocate device memory: code recorded under HIP graph
+ * capture, tight serving loops, and harnesses that forbid hipMalloc. Same arguments, steps and
+ * results as loop_step (the same kernels run), but no caller work space: the work space is a
+ * static device array of LOOP_NOALLOC_SCRATCH_BYTES inside the library, one per device, held
+ * from the library's load until the process ends. The call allocates and frees nothing.
+ * - A shape whose work space (loop_workspace_bytes(Nx, Ns, nloops)) exceeds
+ *   LOOP_NOALLOC_SCRATCH_BYTES is rejected with LOOP_EWORKSPACE before anything is queued.
+ * - The device must have been initialised (loop_init, or any earlier call that creates the
+ *   device's twiddle table); otherwise LOOP_EINVAL.
+ * - Every call on a device shares that device's array, and the array keeps the last call's
+ *   contents. Each call first clears the status word it holds. Calls that overlap on one device
+ *   (on different streams, or from different threads) race on the array: order them on one
+ *   stream.
+ * - status: if not NULL, a device int that receives the call's device status once its work
+ *   has run (0, or LOOP_ENONFINITE as loop_status_sync would report it); NULL to skip. */
+#define LOOP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int loop_step_noalloc(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau, int scheme,
+                      int nsteps, double* J_hist, int* status, void* stream);
+
 /* Centre-symmetric loops (Sec. 3, eq. KS_loop_sym). A loop invariant under
  * Xi: (x, s) -> (-x, s), u -> -u (u odd in x at every s) stays invariant under the flow, and
  * every field of the step then has a fixed parity in x: odd fields have purely imaginary,

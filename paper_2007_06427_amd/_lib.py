@@ -27,7 +27,7 @@ LAYOUT_BAND = 1
 EXPORTS = [
     "loop_init", "loop_shutdown", "loop_workspace_bytes", "loop_workspace_init", "loop_residual",
     "loop_cost", "loop_adjoint_grad", "loop_cost_grad", "loop_to_band", "loop_from_band", "loop_cost_fwd",
-    "loop_cost_bwd", "loop_update_grad", "loop_step", "loop_set_resident",
+    "loop_cost_bwd", "loop_update_grad", "loop_step", "loop_step_noalloc", "loop_set_resident",
     "loop_resident_supported", "loop_step_form", "loop_extrapolate", "loop_converge", "loop_step_xi",
     "loop_step_xi_workspace_bytes", "loop_expanded_grad", "loop_step_expanded", "loop_update", "loop_batch_create", "loop_batch_set_schedule", "loop_batch_set_streams",
     "loop_batch_destroy",
@@ -67,6 +67,7 @@ _SIGS = {
     "loop_cost_bwd": ([_d, _i, _i, _i, _i, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
     "loop_update_grad": ([_d, _i, _i, _i, _i, _p, _p, _p, _p, _d, _i, _p], _i),
     "loop_step": ([_d, _i, _i, _i, _p, _p, _d, _i, _i, _p, _p, _sz, _p], _i),
+    "loop_step_noalloc": ([_d, _i, _i, _i, _p, _p, _d, _i, _i, _p, _p, _p], _i),
     "loop_update": ([_d, _i, _i, _i, _p, _p, _p, _p, _d, _i, _p], _i),
     "loop_batch_create": ([_i, ctypes.POINTER(_d), ctypes.POINTER(_i), ctypes.POINTER(_i),
                            ctypes.POINTER(_p)], _i),

@@ -22,6 +22,13 @@
 
 using namespace lo;
 
+// Work space of loop_step_noalloc, for callers that cannot allocate: one copy per device, held
+// from the library's load until the process ends. Host code never uses this name as an
+// address (on the host it is only a handle): it takes each device's address from
+// hipGetSymbolAddress once (init_scratch) and passes that pointer to the kernels.
+constexpr size_t kScratchBytes = LOOP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace {
 
 // ============================================================================ kernels
@@ -411,6 +418,8 @@ __global__ void k_ws_init(WsHeader* h) {
 }
 
 __global__ void k_ws_clear_status(WsHeader* h) { h->status = 0; }
+
+__global__ void k_copy_status(const WsHeader* h, int* status) { *status = h->status; }
 
 // ============================================================================ batched scheduler
 // A batch of loops of uneven shape advances in one persistent launch. The launch works
@@ -919,6 +928,37 @@ int get_table(const cd** out) {
     }
     g_tables[dev] = tb;
     *out = tb.dev;
+    return LOOP_OK;
+}
+
+// Per device, the address of that device's copy of `scratch` (under g_mu).
+std::map<int, char*> g_scratch;
+
+// Record the current device's scratch address. The call allocates nothing; it fails if the
+// runtime cannot resolve the symbol on this device.
+int init_scratch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LOOP_EHIP;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_scratch.count(dev)) return LOOP_OK;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return LOOP_EHIP;
+    g_scratch[dev] = static_cast<char*>(p);
+    return LOOP_OK;
+}
+
+// The current device's scratch address and twiddle table, without allocating anything: the
+// table must exist already (loop_init, or any earlier call on the device, creates it).
+int device_statics(char** base, const cd** tw) {
+    int st = init_scratch();
+    if (st) return st;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LOOP_EHIP;
+    std::lock_guard<std::mutex> lk(g_mu);
+    const auto t = g_tables.find(dev);
+    if (t == g_tables.end()) return LOOP_EINVAL;
+    *tw = t->second.dev;
+    *base = g_scratch[dev];
     return LOOP_OK;
 }
 
@@ -1474,7 +1514,8 @@ extern "C" {
 
 int loop_init(void) {
     const cd* tw = nullptr;
-    return get_table(&tw);
+    const int st = get_table(&tw);
+    return st ? st : init_scratch();
 }
 
 int loop_shutdown(void) {
@@ -1710,6 +1751,29 @@ int loop_step(double L, int Nx, int Ns, int nloops, double* T, double* uhat, dou
     if (st) return st;
     if ((st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw))) return st;
     return step_impl(s, w, tw, T, reinterpret_cast<cd*>(uhat), dtau, scheme, nsteps, J_hist, (hipStream_t)stream);
+}
+
+int loop_step_noalloc(double L, int Nx, int Ns, int nloops, double* T, double* uhat, double dtau, int scheme,
+                      int nsteps, double* J_hist, int* status, void* stream) {
+    int st = step_args(T, uhat, dtau, scheme, nsteps, J_hist);
+    if (st) return st;
+    if (status && !aligned(status, 4)) return LOOP_EINVAL;
+    if ((st = check_shape(L, Nx, Ns, nloops))) return st;
+    const Shape s = make_shape(L, Nx, Ns, nloops);
+    if (layout(s, nullptr, nullptr) > kScratchBytes) return LOOP_EWORKSPACE;
+    // the device's scratch address and twiddle table, both set up by loop_init: nothing here allocates
+    char* base = nullptr;
+    const cd* tw = nullptr;
+    if ((st = device_statics(&base, &tw))) return st;
+    Work w{};
+    layout(s, base, &w);
+    hipStream_t hs = (hipStream_t)stream;
+    // the previous call's status word is cleared by a kernel (not a memset, so that the call can
+    // be recorded into a HIP graph and replayed)
+    hipLaunchKernelGGL(k_ws_init, dim3(1), dim3(1), 0, hs, reinterpret_cast<WsHeader*>(base));
+    if ((st = step_impl(s, w, tw, T, reinterpret_cast<cd*>(uhat), dtau, scheme, nsteps, J_hist, hs))) return st;
+    if (status) hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(1), 0, hs, reinterpret_cast<const WsHeader*>(base), status);
+    return last_error();
 }
 
 int loop_expanded_grad(double L, int Nx, int Ns, int nloops, const double* T, const double* uhat, double* Ghat,
