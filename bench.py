@@ -357,8 +357,8 @@ def autograd_kernel_bytes(Nx, Ns):
       update   k_update_grad_band reads u_hat, grad; writes u_hat   3S
     16 (10W + 10S) per loop-step; the per-loop scalars (J, dJ/dT, T) are left out."""
     W, S = band(Nx, Ns)
-    return {f"k_colA<{Ns}>": 16 * (S + W), f"k_rowB<{Nx}>": 16 * 2 * W, f"k_colC<{Ns}>": 16 * (W + 2 * S),
-            f"k_colAC<{Ns}>": 16 * (2 * S + 2 * W), f"k_rowD<{Nx}>": 16 * 3 * W, f"k_colE<{Ns}>": 16 * (W + 2 * S),
+    return {f"k_colA<{Ns}>": 16 * (S + W), f"k_rowB<{Nx}>": 16 * 2 * W, f"k_colC<{Ns}, 0>": 16 * (W + 2 * S),
+            f"k_colAC<{Ns}>": 16 * (2 * S + 2 * W), f"k_rowD<{Nx}>": 16 * 3 * W, f"k_colE<{Ns}, 4>": 16 * (W + 2 * S),
             "k_update_grad_band": 16 * 3 * S}
 
 

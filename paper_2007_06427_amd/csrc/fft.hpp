@@ -31,8 +31,10 @@ constexpr int TW_N = 4096;  // twiddle table: tw[t] = exp(-2 pi i t / TW_N)
 
 __device__ __forceinline__ cd cadd(cd a, cd b) { return {a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ cd csub(cd a, cd b) { return {a.x - b.x, a.y - b.y}; }
+// Complex product with two fused multiply-adds (explicit, so every kernel that inlines it
+// rounds it the same way).
 __device__ __forceinline__ cd cmul(cd a, cd b) {
-    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+    return {__builtin_fma(a.x, b.x, -(a.y * b.y)), __builtin_fma(a.x, b.y, a.y * b.x)};
 }
 __device__ __forceinline__ cd cconj(cd a) { return {a.x, -a.y}; }
 __device__ __forceinline__ cd cscale(cd a, double s) { return {a.x * s, a.y * s}; }
@@ -59,6 +61,16 @@ __device__ __forceinline__ cd w16(cd a) {
         return cd{-a.x, -a.y};
     } else if constexpr (mm == 12) {
         return rot90<!INV>(a);
+    } else if constexpr (mm % 4 == 2) {
+        // odd multiples of pi/4: (x, y) (c, sy) with |c| = |sy| = sqrt(1/2), one add and one
+        // product per component
+        constexpr double c = (mm == 2 || mm == 14) ? kSqrtHalf : -kSqrtHalf;
+        constexpr double sy = ((mm == 2 || mm == 6) ? kSqrtHalf : -kSqrtHalf) * (INV ? 1.0 : -1.0);
+        if constexpr (c == sy) {
+            return cd{(a.x - a.y) * c, (a.x + a.y) * c};
+        } else {
+            return cd{(a.x + a.y) * c, (a.y - a.x) * c};
+        }
     } else {
         // cos and sin of 2 pi mm / 16 from the first-octant constants
         constexpr double c = (mm == 1 || mm == 15) ? kCos8 : (mm == 2 || mm == 14) ? kSqrtHalf
@@ -69,7 +81,7 @@ __device__ __forceinline__ cd w16(cd a) {
                            : (mm == 10 || mm == 14) ? -kSqrtHalf : -kCos8;  // 11, 13
         // forward: exp(-i theta) = (c, -s); inverse: (c, s)
         constexpr double sy = INV ? s : -s;
-        return cd{a.x * c - a.y * sy, a.x * sy + a.y * c};
+        return cd{__builtin_fma(a.x, c, -(a.y * sy)), __builtin_fma(a.x, sy, a.y * c)};
     }
 }
 
@@ -213,7 +225,7 @@ __device__ __forceinline__ cd opaque(cd w) {
 
 template <bool INV>
 __device__ __forceinline__ cd cmul_tw(cd a, cd w) {
-    return INV ? cd{a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y} : cmul(a, w);
+    return INV ? cd{__builtin_fma(a.x, w.x, a.y * w.y), __builtin_fma(a.y, w.x, -(a.x * w.y))} : cmul(a, w);
 }
 
 // Apply w^(k r) to element r of butterfly i (elements in slots i + r NB), from the cache.

@@ -40,16 +40,18 @@ __global__ __launch_bounds__(kBlock) void k_colA(Shape sh, Work w, const cd* __r
 
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_rowB(Shape sh, Work w, const cd* __restrict__ tw) {
-    __shared__ cd lds[RowG<M>::LDS];
+    __shared__ cd lds[RowG<M>::LDS_B];
     row_pass_B<M>(sh, blockIdx.x, w, lds, tw);
 }
 
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_colC(Shape sh, const double* __restrict__ T, Work w, int mode,
-                                                 double dtau, int scheme, const cd* __restrict__ tw) {
+// The column kernels are compiled per mode, so that each allocates registers for its own
+// work only (the residual-only forward has no inverse transform).
+template <int N, int MODE>
+__global__ __launch_bounds__(kBlock) void k_colC(Shape sh, const double* __restrict__ T, Work w, double dtau,
+                                                 int scheme, const cd* __restrict__ tw) {
     __shared__ cd ex[ColG<N>::LDS];
     __shared__ double red[2 * kBlock / 64];
-    col_pass_C<N>(sh, blockIdx.x, T, w, mode, dtau, scheme, ex, red, tw);
+    col_pass_C<N>(sh, blockIdx.x, T, w, MODE, dtau, scheme, ex, red, tw);
 }
 
 template <int M>
@@ -60,11 +62,11 @@ __global__ __launch_bounds__(kBlock) void k_rowD(Shape sh, Work w, double* T, in
     row_pass_D<M>(sh, blockIdx.x, w, T, mode, dtau, J_hist, Jout, dJdTout, lds, tw);
 }
 
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_colE(Shape sh, Work w, int mode, double dtau, int scheme, int fuseA,
+template <int N, int MODE>
+__global__ __launch_bounds__(kBlock) void k_colE(Shape sh, Work w, double dtau, int scheme, int fuseA,
                                                  const cd* __restrict__ tw, const double* __restrict__ T) {
     __shared__ cd ex[ColG<N>::LDS];
-    col_pass_E<N>(sh, blockIdx.x, w, mode, dtau, scheme, fuseA != 0, ex, tw, T);
+    col_pass_E<N>(sh, blockIdx.x, w, MODE, dtau, scheme, fuseA != 0, ex, tw, T);
 }
 
 template <int N>
@@ -1059,7 +1061,7 @@ struct TraceScope {
     hipEvent_t a = nullptr;
     hipStream_t st = nullptr;
     std::string name;
-    TraceScope(const char* base, int size, hipStream_t s) : TraceScope(base, size, 0, s) {}
+    TraceScope(const char* base, int size, hipStream_t s) : TraceScope(base, size, -1, s) {}
     TraceScope(const char* base, int size, int size2, hipStream_t s) {
         if (!g_trace_on.load(std::memory_order_relaxed)) return;
         std::lock_guard<std::mutex> g(g_trace_mu);
@@ -1071,7 +1073,7 @@ struct TraceScope {
         }
         st = s;
         name = std::string(base);
-        if (size > 0) name += "<" + std::to_string(size) + (size2 > 0 ? ", " + std::to_string(size2) : "") + ">";
+        if (size > 0) name += "<" + std::to_string(size) + (size2 >= 0 ? ", " + std::to_string(size2) : "") + ">";
     }
     ~TraceScope() {
         if (!a) return;
@@ -1131,10 +1133,20 @@ int launch_B(const Shape& s, const Work& w, const cd* tw, hipStream_t st) {
 }
 int launch_C(const Shape& s, const double* T, const Work& w, int mode, double dtau, int scheme, const cd* tw,
              hipStream_t st) {
-    LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colC", S_, st);
-                   hipLaunchKernelGGL(k_colC<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, T, w, mode,
-                                           dtau, scheme, tw));
-    return LOOP_OK;
+    auto launch = [&](auto md) {
+        constexpr int MD = decltype(md)::value;
+        LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colC", S_, MD, st);
+                       hipLaunchKernelGGL((k_colC<S_, MD>), dim3(col_blocks(s)), dim3(kBlock), 0, st, s, T, w, dtau,
+                                          scheme, tw));
+        return LOOP_OK;
+    };
+    switch (mode) {
+        case MODE_RESIDUAL: return launch(std::integral_constant<int, MODE_RESIDUAL>{});
+        case MODE_COST: return launch(std::integral_constant<int, MODE_COST>{});
+        case MODE_GRAD: return launch(std::integral_constant<int, MODE_GRAD>{});
+        case MODE_STEP: return launch(std::integral_constant<int, MODE_STEP>{});
+        default: return LOOP_EINVAL;
+    }
 }
 int launch_D(const Shape& s, const Work& w, double* T, int mode, double dtau, double* J_hist, double* Jout,
              double* dJdTout, const cd* tw, hipStream_t st) {
@@ -1145,10 +1157,19 @@ int launch_D(const Shape& s, const Work& w, double* T, int mode, double dtau, do
 }
 int launch_E(const Shape& s, const Work& w, int mode, double dtau, int scheme, int fuseA, const cd* tw,
              hipStream_t st, const double* T = nullptr) {
-    LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colE", S_, st);
-                   hipLaunchKernelGGL(k_colE<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, mode, dtau,
-                                           scheme, fuseA, tw, T));
-    return LOOP_OK;
+    auto launch = [&](auto md) {
+        constexpr int MD = decltype(md)::value;
+        LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colE", S_, MD, st);
+                       hipLaunchKernelGGL((k_colE<S_, MD>), dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, dtau,
+                                          scheme, fuseA, tw, T));
+        return LOOP_OK;
+    };
+    switch (mode) {
+        case MODE_GRAD: return launch(std::integral_constant<int, MODE_GRAD>{});
+        case MODE_STEP: return launch(std::integral_constant<int, MODE_STEP>{});
+        case MODE_ADJOINT: return launch(std::integral_constant<int, MODE_ADJOINT>{});
+        default: return LOOP_EINVAL;
+    }
 }
 int launch_AC(const Shape& s, const Work& w, const cd* tw, hipStream_t st) {
     LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colAC", S_, st);
@@ -1458,7 +1479,7 @@ unsigned elem_blocks(size_t n) {
 }  // namespace
 
 namespace {
-// Argument checks of the stepping entry points.
+// Argument checks shared by loop_step and loop_step_noalloc.
 int step_args(const double* T, const double* uhat, double dtau, int scheme, int nsteps, const double* J_hist) {
     if (!aligned(T, 8) || !aligned(uhat, 16) || (J_hist && !aligned(J_hist, 8))) return LOOP_EINVAL;
     if (!(dtau > 0.0) || !std::isfinite(dtau) || (scheme != 0 && scheme != 1) || nsteps < 0) return LOOP_EINVAL;
@@ -1702,16 +1723,14 @@ int loop_cost_bwd(double L, int Nx, int Ns, int nloops, int layout, const double
     if ((st = bind_state(s, w, layout, u, hs))) return st;
     w.R = reinterpret_cast<const cd*>(rsave);
     w.gJ = gJ;
+    w.dJdT_in = dJdT;
+    w.grad_T = grad_T;  // pass E writes gJ dJ/dT
     cd* gout = w.G;  // band result in the work space, converted below (rfft layout)
     if (layout == LOOP_LAYOUT_BAND) w.G = reinterpret_cast<cd*>(grad_u);
     if ((st = launch_AC(s, w, tw, hs))) return st;
     if ((st = launch_D(s, w, const_cast<double*>(T), MODE_ADJOINT, 0.0, nullptr, nullptr, nullptr, tw, hs))) return st;
     if ((st = launch_E(s, w, MODE_ADJOINT, 0.0, 0, 0, tw, hs, T))) return st;
     if (layout == LOOP_LAYOUT_RFFT) launch_from_band(s, gout, reinterpret_cast<cd*>(grad_u), hs);
-    if (grad_T) {
-        TraceScope ts_("k_grad_T", 0, hs);
-        hipLaunchKernelGGL(k_grad_T, dim3((nloops + 255) / 256), dim3(256), 0, hs, nloops, gJ, dJdT, grad_T);
-    }
     return last_error();
 }
 

@@ -8,9 +8,11 @@
 //
 // Pass A (columns): A(j, s_n) = sum_k u_hat_{j,k} e^{2 pi i n k / N}, an inverse
 //                   s-transform of each retained column.
-// Pass B (rows):    u and u_x at (x_m, s_n) from inverse x-transforms of A(., s_n) and of
-//                   i q A(., s_n); w = u u_x; B(j, s_n) = forward x-transform of w, j < C.
-//                   (Each inverse transform carries two rows of one field.)
+// Pass B (rows):    u at (x_m, s_n) from the inverse x-transform of A(., s_n); u^2 on the
+//                   grid; B(j, s_n) = (i q_j / 2) times the forward x-transform of u^2, j < C,
+//                   which is the transform of u u_x = (1/2) (u^2)_x. Rows longer than
+//                   kSquareMaxM take u_x from a second inverse transform and the product u u_x
+//                   instead (accuracy, see kSquareMaxM). (Each transform carries two rows.)
 // Pass C (columns): w_hat = forward s-transform of B, then the residual of eq. KS_R,
 //                     r_hat = -(i omega/T) u_hat - w_hat + q^2 u_hat - q^4 u_hat.
 //                   Per-column partial sums of J and dJ/dT. The linear part of the flow,
@@ -25,11 +27,12 @@
 //                   runs pass A of the next step on the new column, while it is still in
 //                   registers.
 //
-// u u_x and u r_x are formed as products in physical space (the paper's pseudo-spectral
-// treatment), not as (1/2)(u^2)_x. This keeps the round-off of high modes at the size of
-// the product instead of amplifying it by q_max. Every product is of two band-limited fields
-// on the full grid, so it is free of aliasing inside the band. Truncation to the band is
-// implicit: only retained modes are ever formed.
+// u u_x is formed as (1/2) (u^2)_x on rows of up to kSquareMaxM points (the square in physical
+// space, the paper's pseudo-spectral treatment of products, and the derivative in spectral
+// space) and as the product u * u_x on longer rows; u r_x is always a product in physical space.
+// Every product is of band-limited fields on the full grid, so it is free of aliasing inside
+// the band, and differentiating the square there is exact. Truncation to the band is implicit:
+// only retained modes are ever formed.
 //
 // Device layouts (complex values, interleaved doubles), one loop after another:
 //   band state U, G   [l][j][kk]  j < C, kk < NB: kk = k (k >= 0), kk = k + NB (k < 0)
@@ -77,6 +80,8 @@ struct Work {
     int* status;      // sticky device status
     const cd* R;      // [l][j][kk] saved residual r_hat (MODE_ADJOINT)
     const double* gJ;  // [l] cotangent of J (MODE_ADJOINT; null: all ones)
+    const double* dJdT_in;  // [l] dJ/dT of the forward (MODE_ADJOINT)
+    double* grad_T;   // [l] gJ dJ/dT, written by pass E (MODE_ADJOINT; null: skipped)
     int herm0;        // U is caller-owned: read column 0 through its Hermitian part
 };
 
@@ -319,6 +324,8 @@ __device__ __forceinline__ void col_pass_E(const Shape& sh, int block, const Wor
     cd* g = w.G + col * sh.NB;
     cd* u = w.U + col * sh.NB;
     const cd* r = w.R + col * sh.NB;
+    if (mode == MODE_ADJOINT && w.grad_T && p.active && p.j == 0 && p.t == 0)
+        w.grad_T[p.l] = (w.gJ ? w.gJ[p.l] : 1.0) * w.dJdT_in[p.l];
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) {
         const int e = p.t + m * G::TPF;
@@ -356,7 +363,7 @@ __device__ __forceinline__ void col_pass_E(const Shape& sh, int block, const Wor
         }
         v[m] = x;
     }
-    if (fuseA) col_inverse_store<N>(sh, p, v, w.A, ex, twc);
+    if (mode == MODE_STEP && fuseA) col_inverse_store<N>(sh, p, v, w.A, ex, twc);
 }
 
 // ---------------------------------------------------------------------------- row passes
@@ -485,6 +492,129 @@ __device__ __forceinline__ cd herm_ext(const cd* tile, int TS, int r, int e, int
 // Spectrum of f + i g for two real rows f, g given by their half spectra (packed complex).
 __device__ __forceinline__ cd pack2(cd f, cd g) { return cd{f.x - g.y, f.y + g.x}; }
 
+// herm_ext for the elements e = t + m TPF (m = 0 .. PT-1) that thread t of a row transform
+// holds, with the band limit Kx = (M-1)/3 of an M-point row known at compile time. A slot
+// whose elements all lie in the band reads them directly (e <= Kx) or as conjugates of their
+// partners (e >= M - Kx); a slot wholly outside the band is zero; only a slot that straddles
+// a band edge selects per lane. The values are herm_ext's, bit for bit.
+template <int M, int PT, int m>
+__device__ __forceinline__ cd herm_slot(const cd* tile, int TS, int r, int t) {
+    constexpr int TPF = M / PT, Kx = (M - 1) / 3;
+    constexpr int lo = m * TPF, hi = lo + TPF - 1;
+    if constexpr (hi <= Kx) {
+        const cd v = tile[(lo + t) * TS + r];
+        if constexpr (lo == 0) return cd{v.x, t == 0 ? 0.0 : v.y};  // X_0 is read as real
+        return v;
+    } else if constexpr (lo >= M - Kx) {
+        const cd v = tile[(M - lo - t) * TS + r];
+        return cd{v.x, -v.y};
+    } else if constexpr (lo > Kx && hi < M - Kx) {
+        return cd{0.0, 0.0};
+    } else {
+        return herm_ext(tile, TS, r, lo + t, M, Kx);
+    }
+}
+
+// va[m] = pack2 of rows ra and rb of a tile, slot by slot (see herm_slot).
+template <int M, int PT, int m = 0>
+__device__ __forceinline__ void herm_pack(const cd* tile, int TS, int ra, int rb, int t, cd* va) {
+    if constexpr (m < PT) {
+        va[m] = pack2(herm_slot<M, PT, m>(tile, TS, ra, t), herm_slot<M, PT, m>(tile, TS, rb, t));
+        herm_pack<M, PT, m + 1>(tile, TS, ra, rb, t, va);
+    }
+}
+
+// herm_pack, and in vb the x-derivatives of the same rows (i q times each element, q of the
+// signed frequency of slot m).
+template <int M, int PT, int m = 0>
+__device__ __forceinline__ void herm_pack_dx(const cd* tile, int TS, int ra, int rb, int t, double dq, cd* va,
+                                             cd* vb) {
+    if constexpr (m < PT) {
+        constexpr int TPF = M / PT;
+        const int e = t + m * TPF;
+        const double q = dq * (double)((e <= M / 2) ? e : e - M);
+        const cd a = herm_slot<M, PT, m>(tile, TS, ra, t), b = herm_slot<M, PT, m>(tile, TS, rb, t);
+        va[m] = pack2(a, b);
+        vb[m] = pack2(cd{-q * a.y, q * a.x}, cd{-q * b.y, q * b.x});
+        herm_pack_dx<M, PT, m + 1>(tile, TS, ra, rb, t, dq, va, vb);
+    }
+}
+
+// Pass B forms u u_x as (1/2) (u^2)_x (two transforms per pair of rows) for rows of up to
+// kSquareMaxM points, and as the product u * u_x (three transforms) for longer rows.
+// Differentiating the square multiplies the round-off of mode j by q_j / 2, against the
+// product's round-off of order |u u_x|: the ratio grows as Kx over the input's dominant mode
+// index. Measured against the FP64 oracle on low-mode loops (|j| <= 8), the flow G of the
+// square form errs by 1.1e-13 at 128 x 64, 4.9e-13 at 256 x 1024 and 3.8e-12 at 512 x 32
+// (normwise), the product form by 1.7e-14, 3.0e-14 and 1.3e-13; with Kx <= 42 the square form
+// stays inside the 1e-12 bound even for a loop made of its lowest mode.
+constexpr int kSquareMaxM = 128;
+
+// Forward transform of the pair's product values va, then the split of the result
+// Z = W_a + i W_b into the two rows' half spectra, W_a(j) = (Z_j + conj Z_{M-j}) / 2 and
+// W_b(j) = (Z_j - conj Z_{M-j}) / (2i), scaled by 1/M, written to tile[j][r] over the
+// inputs' LDS. With DX the rows' spectra are differentiated on the way, i q_j / 2 W (the half
+// derivative of a square).
+template <int M, int PT, bool DX>
+__device__ __forceinline__ void row_forward_split(const Shape& sh, cd* va, cd* lds, cd* ex, int t,
+                                                  const TwCache<M, PT>& twc) {
+    using G = RowG<M, PT>;
+    fft<M, G::PT, false>(va, t, ex, twc);
+#pragma unroll
+    for (int m = 0; m < G::PT; ++m) ex[xpos(t + m * G::TPF)] = va[m];
+    wave_lds_sync();
+    const int lane = threadIdx.x % 64;
+    const int pw0 = (threadIdx.x / 64) * G::PW;
+    const int nout = 2 * G::PW * sh.C;
+    const double s = 0.5 / M;
+    const double hq = (kTwoPi / sh.L) * (0.25 / M);  // q_j / 2 per unit j, with the 1/(2M) of the split
+    cd outv[G::NOUT];
+#pragma unroll
+    for (int i = 0; i < G::NOUT; ++i) {
+        const int idx = lane + 64 * i;
+        if (idx < nout) {
+            const int pp = pw0 + idx / (2 * sh.C);
+            const int rem = idx % (2 * sh.C);
+            const int j = rem >> 1;
+            const cd* e2 = lds + pp * xlen<M>();
+            const cd a = e2[xpos(j)];
+            const cd b = e2[xpos((M - j) & (M - 1))];
+            if constexpr (DX) {
+                const double c = hq * j;
+                outv[i] = (rem & 1) ? cd{c * (a.x - b.x), c * (a.y + b.y)} : cd{c * (b.y - a.y), c * (a.x + b.x)};
+            } else {
+                outv[i] = (rem & 1) ? cd{(a.y + b.y) * s, (b.x - a.x) * s} : cd{(a.x + b.x) * s, (a.y - b.y) * s};
+            }
+        }
+    }
+    __syncthreads();  // every wave is done with its exchange region: reuse as the output tile
+#pragma unroll
+    for (int i = 0; i < G::NOUT; ++i) {
+        const int idx = lane + 64 * i;
+        if (idx < nout) {
+            const int pp = pw0 + idx / (2 * sh.C);
+            const int rem = idx % (2 * sh.C);
+            lds[(rem >> 1) * G::TS + ((rem & 1) ? G::P + pp : pp)] = outv[i];
+        }
+    }
+    __syncthreads();
+}
+
+// u u_x = (1/2) (u^2)_x on rows a and b of a pair: one inverse transform of u_a + i u_b, the
+// squares (u_a^2) + i (u_b^2) in physical space, one forward transform, and the split with the
+// factor i q_j / 2. Both fields are band-limited, so (u^2)_x of the band equals the band of
+// 2 u u_x exactly; one transform of three is saved.
+template <int M, int PT = RowG<M>::PT>
+__device__ __forceinline__ void row_square_dx(const Shape& sh, cd* va, cd* lds, int t, int p,
+                                              const TwCache<M, PT>& twc) {
+    cd* ex = lds + p * xlen<M>();
+    __syncthreads();  // every wave has read its inputs from the tile: the tile is free
+    fft<M, PT, true>(va, t, ex, twc);
+#pragma unroll
+    for (int m = 0; m < PT; ++m) va[m] = cd{va[m].x * va[m].x, va[m].y * va[m].y};
+    row_forward_split<M, PT, true>(sh, va, lds, ex, t, twc);
+}
+
 // Products of two real fields f, g on rows a and b of a pair. The two inverse x-transforms
 // take the rows of one field at a time (va = f_a + i f_b, vb = g_a + i g_b), so each transform
 // carries values of one scale; packing f and g of one row together would let the round-off
@@ -501,40 +631,7 @@ __device__ __forceinline__ void row_products(const Shape& sh, cd* va, cd* vb, cd
     fft<M, G::PT, true>(vb, t, ex, twc);
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) va[m] = cd{va[m].x * vb[m].x, va[m].y * vb[m].y};
-    fft<M, G::PT, false>(va, t, ex, twc);
-#pragma unroll
-    for (int m = 0; m < G::PT; ++m) ex[xpos(t + m * G::TPF)] = va[m];
-    wave_lds_sync();
-    // split Z = W_a + i W_b: W_a(j) = (Z_j + conj Z_{M-j}) / 2, W_b(j) = (Z_j - conj Z_{M-j}) / (2i)
-    const int lane = threadIdx.x % 64;
-    const int pw0 = (threadIdx.x / 64) * G::PW;
-    const int nout = 2 * G::PW * sh.C;
-    const double s = 0.5 / M;
-    cd outv[G::NOUT];
-#pragma unroll
-    for (int i = 0; i < G::NOUT; ++i) {
-        const int idx = lane + 64 * i;
-        if (idx < nout) {
-            const int pp = pw0 + idx / (2 * sh.C);
-            const int rem = idx % (2 * sh.C);
-            const int j = rem >> 1;
-            const cd* e2 = lds + pp * xlen<M>();
-            const cd a = e2[xpos(j)];
-            const cd b = e2[xpos((M - j) & (M - 1))];
-            outv[i] = (rem & 1) ? cd{(a.y + b.y) * s, (b.x - a.x) * s} : cd{(a.x + b.x) * s, (a.y - b.y) * s};
-        }
-    }
-    __syncthreads();  // every wave is done with its exchange region: reuse as the output tile
-#pragma unroll
-    for (int i = 0; i < G::NOUT; ++i) {
-        const int idx = lane + 64 * i;
-        if (idx < nout) {
-            const int pp = pw0 + idx / (2 * sh.C);
-            const int rem = idx % (2 * sh.C);
-            lds[(rem >> 1) * G::TS + ((rem & 1) ? G::P + pp : pp)] = outv[i];
-        }
-    }
-    __syncthreads();
+    row_forward_split<M, PT, false>(sh, va, lds, ex, t, twc);
 }
 
 // DMA selects load_rows_lds over load_rows (tiles of 64 rows or more). PT below the default
@@ -550,7 +647,6 @@ __device__ __forceinline__ void row_pass_B(const Shape& sh, int block, const Wor
     const int t = threadIdx.x % G::TPF, p = threadIdx.x / G::TPF;
     TwCache<M, PT> twc;
     tw_cache_load<M, PT>(twc, t, tw);
-    const double dq = kTwoPi / sh.L;
     auto sub = [&](size_t g0) {
         {
             const cd* const src[1] = {w.A};
@@ -560,16 +656,15 @@ __device__ __forceinline__ void row_pass_B(const Shape& sh, int block, const Wor
                 load_rows<G::ROWS, G::CMAX, G::TS, G::TILE, 1>(lds, src, g0, sh, nrows);
         }
         __syncthreads();
-        cd va[PT], vb[PT];
-#pragma unroll
-        for (int m = 0; m < PT; ++m) {
-            const int e = t + m * G::TPF;
-            const double q = dq * (double)((e <= M / 2) ? e : e - M);
-            const cd a = herm_ext(lds, G::TS, p, e, M, sh.Kx), b = herm_ext(lds, G::TS, G::P + p, e, M, sh.Kx);
-            va[m] = pack2(a, b);                                           // u, rows a and b
-            vb[m] = pack2(cd{-q * a.y, q * a.x}, cd{-q * b.y, q * b.x});  // u_x = (i q u_hat), rows a and b
+        if constexpr (M <= kSquareMaxM) {
+            cd va[PT];
+            herm_pack<M, PT>(lds, G::TS, p, G::P + p, t, va);  // u, rows a and b
+            row_square_dx<M, PT>(sh, va, lds, t, p, twc);
+        } else {
+            cd va[PT], vb[PT];
+            herm_pack_dx<M, PT>(lds, G::TS, p, G::P + p, t, kTwoPi / sh.L, va, vb);  // u and u_x, rows a and b
+            row_products<M, PT>(sh, va, vb, lds, t, p, twc);
         }
-        row_products<M, PT>(sh, va, vb, lds, t, p, twc);
         store_rows<G::ROWS, G::CMAX>(lds, G::TS, w.BD, g0, sh, nrows);
     };
     const size_t gb = (size_t)block * RowG<M>::ROWS;
@@ -655,12 +750,8 @@ __device__ __forceinline__ void row_pass_D(const Shape& sh, int block, const Wor
         }
         __syncthreads();
         cd va[PT], vb[PT];
-#pragma unroll
-        for (int m = 0; m < PT; ++m) {
-            const int e = t + m * G::TPF;
-            va[m] = pack2(herm_ext(tA, G::TS, p, e, M, sh.Kx), herm_ext(tA, G::TS, G::P + p, e, M, sh.Kx));  // u
-            vb[m] = pack2(herm_ext(tC, G::TS, p, e, M, sh.Kx), herm_ext(tC, G::TS, G::P + p, e, M, sh.Kx));  // r_x
-        }
+        herm_pack<M, PT>(tA, G::TS, p, G::P + p, t, va);  // u
+        herm_pack<M, PT>(tC, G::TS, p, G::P + p, t, vb);  // r_x
         row_products<M, PT>(sh, va, vb, lds, t, p, twc);
         store_rows<G::ROWS, G::CMAX>(lds, G::TS, w.BD, g0, sh, nrows);
     };

@@ -94,27 +94,41 @@ __device__ __forceinline__ void res_row_products(const Shape& sh, cd* va, cd* vb
     wave_lds_sync();  // the exchange region is reused by this group's next transform
 }
 
-// Pass B for the pairs of row tile `tile`: X = (u u_x) per row, from A.
+// Pass B for the pairs of row tile `tile`: X = (u u_x) = (1/2) (u^2)_x per row, from A (the
+// same arithmetic as row_square_dx; resident rows are never longer than kSquareMaxM).
 template <int M>
 __device__ __forceinline__ void res_row_B(const Shape& sh, int tile, const cd* A, cd* X, cd* exr,
                                           const cd* __restrict__ tw) {
     using G = RowG<M>;
+    static_assert(M <= kSquareMaxM, "the resident form takes the square form of u u_x");
     const ResRowLane<M> ln;
     const int a = tile * G::ROWS + ln.p, b = a + G::P;
     const bool oka = a < sh.N, okb = b < sh.N;
     TwCache<M, G::PT> twc;
     tw_cache_load<M, G::PT>(twc, ln.t, tw);
-    const double dq = kTwoPi / sh.L;
-    cd va[G::PT], vb[G::PT];
+    cd va[G::PT];
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) {
         const int e = ln.t + m * G::TPF;
-        const double q = dq * (double)((e <= M / 2) ? e : e - M);
-        const cd ua = res_herm(A, sh.N, a, oka, e, M, sh.Kx), ub = res_herm(A, sh.N, b, okb, e, M, sh.Kx);
-        va[m] = pack2(ua, ub);
-        vb[m] = pack2(cd{-q * ua.y, q * ua.x}, cd{-q * ub.y, q * ub.x});
+        va[m] = pack2(res_herm(A, sh.N, a, oka, e, M, sh.Kx), res_herm(A, sh.N, b, okb, e, M, sh.Kx));
     }
-    res_row_products<M>(sh, va, vb, exr + ln.p * res_rxs<M>(), ln.t, X, a, b, oka, okb, twc);
+    cd* ex = exr + ln.p * res_rxs<M>();
+    fft<M, G::PT, true>(va, ln.t, ex, twc);
+#pragma unroll
+    for (int m = 0; m < G::PT; ++m) va[m] = cd{va[m].x * va[m].x, va[m].y * va[m].y};
+    fft<M, G::PT, false>(va, ln.t, ex, twc);
+#pragma unroll
+    for (int m = 0; m < G::PT; ++m) ex[xpos(ln.t + m * G::TPF)] = va[m];
+    wave_lds_sync();
+    const double hq = (kTwoPi / sh.L) * (0.25 / M);
+    for (int j = ln.t; j < sh.C; j += G::TPF) {
+        const cd za = ex[xpos(j)];
+        const cd zb = ex[xpos((M - j) & (M - 1))];
+        const double c = hq * j;
+        if (oka) X[j * sh.N + a] = cd{c * (zb.y - za.y), c * (za.x + zb.x)};
+        if (okb) X[j * sh.N + b] = cd{c * (za.x - zb.x), c * (za.y + zb.y)};
+    }
+    wave_lds_sync();  // the exchange region is reused by this group's next transform
 }
 
 // Pass D for the pairs of row tile `tile`: X = (u r_x) per row, from A and X (r_x), in place.

@@ -81,7 +81,7 @@ SHAPES = [
 @pytest.mark.parametrize("kind", ["seeded", "full"])
 def test_entry_points_match_oracle(api, Nx, Ns, L, kind):
     nl = 3
-    u, T = make_batch(Nx, Ns, L, nl, seed=Nx * 7919 + Ns + (0 if kind == "seeded" else 1))
+    u, T = make_batch(Nx, Ns, L, nl, seed=Nx * 7919 + Ns + (0 if kind == "seeded" else 1), kind=kind)
     ud, Td = to_dev(u, T)
     r = api.loop_residual(ud, Td, L).cpu().numpy()
     J = api.loop_cost(ud, Td, L).cpu().numpy()
