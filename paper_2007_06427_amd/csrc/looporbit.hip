@@ -1113,7 +1113,7 @@ void host_size_switch(int n, F&& f) {
 }
 
 unsigned col_blocks(const Shape& s) {
-    const int F = 8 * kBlock / s.N;  // columns per block
+    const int F = col_per_block(s.N);  // columns per block
     return (unsigned)(((size_t)s.nloops * s.C + F - 1) / F);
 }
 unsigned row_blocks(const Shape& s) {
@@ -1261,7 +1261,7 @@ size_t xi_layout(const Shape& s, char* base, XiWork* w) {
 }
 
 unsigned xi_col_blocks(const Shape& s) {
-    const int F = 8 * kBlock / s.N;  // column pairs per block
+    const int F = col_per_block(s.N);  // column pairs per block
     return (unsigned)(((size_t)s.nloops * ((s.Kx + 1) / 2) + F - 1) / F);
 }
 
@@ -1400,15 +1400,16 @@ struct BatchPlan {
     hipEvent_t ev_fork = nullptr, ev_lag[3] = {nullptr, nullptr, nullptr}, ev_join[3] = {nullptr, nullptr, nullptr};
 };
 
-int col_tiles(const Shape& s) { return (s.C + 2048 / s.N - 1) / (2048 / s.N); }
+int col_tiles(const Shape& s) { return (s.C + col_per_block(s.N) - 1) / col_per_block(s.N); }
 int row_tiles(const Shape& s) {
     const int rows = 4096 / s.M;
     return (s.N + rows - 1) / rows;
 }
 size_t pass_lds_bytes(const Shape& s) {
-    const size_t col = 2304;  // F * (N + N/8) with F = 2048 / N
+    const size_t col = (size_t)col_per_block(s.N) * (s.N + s.N / 8);  // F columns of N + N/8 values
     const int rows = 4096 / s.M, cmax = (s.M - 1) / 3 + 1;
-    const size_t row = std::max<size_t>(2 * (size_t)cmax * (rows + 1), 2304);
+    // two input tiles, or the exchange regions: kBlock / (M/8) pairs of 9M/8 values (rows <= 512)
+    const size_t row = std::max<size_t>(2 * (size_t)cmax * (rows + 1), (size_t)kBlock * 9);
     return std::max(col, row) * sizeof(cd);
 }
 // Dynamic LDS of one pass of the launch-per-pass form for a loop of this shape (row passes:

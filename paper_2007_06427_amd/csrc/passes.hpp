@@ -117,10 +117,18 @@ __device__ __forceinline__ double wsum_lanes(double x, int width) {
 // ---------------------------------------------------------------------------- column passes
 // TPF = N/PT threads per column transform, F = kBlock / TPF columns per block, thread
 // tid -> t = tid % TPF (position within the transform), f = tid / TPF (column in block).
-// Column c = block * F + f runs over nloops * C columns, loop-major.
+// Column c = block * F + f runs over nloops * C columns, loop-major. Every column length takes
+// 8 points per thread: a 1024-point column spans two wavefronts (radix 8, 8, 8, 2, block
+// barriers between stages). 16 points per thread, one wavefront per column and two exchanges,
+// measured slower on 64 loops of 256 x 1024 (pass C 57.8 against 52.8 us, the reverse pass's
+// column pass 79.9 against 73.9 us): the LDS of a column is the same, so a CU holds the same
+// columns, on half the wavefronts.
+__host__ __device__ constexpr int col_pt(int) { return 8; }
+__host__ __device__ constexpr int col_per_block(int N) { return kBlock / (N / col_pt(N)); }
+
 template <int N>
 struct ColG {
-    static constexpr int PT = 8;
+    static constexpr int PT = col_pt(N);
     static constexpr int TPF = N / PT;
     static constexpr int F = kBlock / TPF;
     static constexpr int LDS = F * xlen<N>();  // complex values of exchange space per block

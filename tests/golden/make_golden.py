@@ -1,7 +1,8 @@
 """Write the stored trajectory fixtures under tests/golden/ from the CPU oracle alone.
 
-Run from the repository root:  python tests/golden/make_golden.py
-It imports only the oracle and the seeded input generator.
+Run from the repository root:  python tests/golden/make_golden.py [plain64x128]
+(the argument writes the 64 x 128 log alone). It imports only the oracle and the seeded input
+generator.
 """
 import json
 import os
@@ -35,6 +36,25 @@ def trajectory(c, steps, scheme, dtau, marks):
         "Ns": spec.Ns, "T0": spec.T, "dtau": dtau, "scheme": "imex" if scheme == K.IMEX else "explicit",
         "steps": steps, "J_hist_marks": {str(m): float(Jh[m]) for m in marks},
         "T_final": float(T), "uhat_final_band": band_list(u, spec.Nx, spec.Ns),
+    }
+
+
+def logged(c, steps, scheme, dtau, every):
+    """Workload c's seed run for `steps` steps, with J and T logged at the start of every
+    `every`-th step (J(tau) and T(tau) at tau = n dtau, n = 0, every, 2 every, ...) and the
+    final state."""
+    spec = loopgen.config_loops(c)[0]
+    u, T = spec.uhat, spec.T
+    J_log, T_log = [], []
+    for _ in range(steps // every):
+        T_log.append(float(T))
+        u, T, Jh = K.step(u, T, spec.L, dtau, scheme, every)
+        J_log.append(float(Jh[0]))
+    return {
+        "workload": loopgen.CONFIGS[c]["name"], "seed": spec.seed, "L": spec.L, "Nx": spec.Nx,
+        "Ns": spec.Ns, "T0": spec.T, "dtau": dtau, "scheme": "imex" if scheme == K.IMEX else "explicit",
+        "steps": steps, "log_every": every, "J_log": J_log, "T_log": T_log,
+        "J_final": float(K.cost(u, T, spec.L)), "T_final": float(T), "uhat_final_band": band_list(u, spec.Nx, spec.Ns),
     }
 
 
@@ -73,7 +93,12 @@ def driven(c, dtau, scheme, jtol, stride, accelerate):
             "abs_uhat_final_band": [[j, k, abs(complex(re, im))] for j, k, re, im in band_list(u, spec.Nx, spec.Ns)]}
 
 
-def main():
+def main(only=None):
+    if only == "plain64x128":
+        data = logged(2, 20000, K.IMEX, 5e-5, 10)
+        with open(os.path.join(HERE, "oracle_traj_plain64x128.json"), "w") as f:
+            json.dump(data, f)
+        return
     data = trajectory(1, 2000, K.EXPLICIT, 1e-4, [0, 1, 10, 100, 1000, 1999])
     with open(os.path.join(HERE, "oracle_traj_plain32x32.json"), "w") as f:
         json.dump(data, f, indent=1)
@@ -81,6 +106,9 @@ def main():
     data.pop("uhat_final_band")
     with open(os.path.join(HERE, "oracle_traj_plain64x128_200.json"), "w") as f:
         json.dump(data, f, indent=1)
+    data = logged(2, 20000, K.IMEX, 5e-5, 10)
+    with open(os.path.join(HERE, "oracle_traj_plain64x128.json"), "w") as f:
+        json.dump(data, f)
     data = converged(1, 0.05, K.IMEX, 1e-10, 2000)
     with open(os.path.join(HERE, "oracle_converged_plain32x32.json"), "w") as f:
         json.dump(data, f, indent=1)
@@ -93,4 +121,4 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1] if len(sys.argv) > 1 else None)

@@ -54,6 +54,23 @@ def test_oracle_trajectory_regression_plain32x32():
         assert abs(u[k % spec.Ns, j] - complex(re, im)) <= 1e-12 * (1 + abs(complex(re, im)))
 
 
+def test_oracle_log_plain64x128_prefix_and_descent():
+    """The 64 x 128 workload's 20 000-step IMEX log (J and T every 10 steps): the oracle
+    reproduces its first 2000 steps, J never increases along it (the flow descends J, eq.
+    J_variation) and T moves by the explicit Euler steps of dJ/dT, which this flow keeps small."""
+    g = load("oracle_traj_plain64x128.json")
+    spec = loopgen.config_loops(2)[0]
+    assert spec.seed == g["seed"] and spec.T == g["T0"] and g["log_every"] == 10 and len(g["J_log"]) == 2000
+    u, T = spec.uhat, spec.T
+    for i in range(200):
+        assert abs(T - g["T_log"][i]) <= 1e-12 * abs(T)
+        u, T, Jh = K.step(u, T, spec.L, g["dtau"], K.IMEX, 10)
+        assert abs(Jh[0] - g["J_log"][i]) <= 1e-12 * abs(Jh[0])
+    J = np.array(g["J_log"] + [g["J_final"]])
+    assert np.all(np.diff(J) <= 0) and J[-1] < 2e-3 * J[0]
+    assert np.all(np.abs(np.diff(g["T_log"])) < 1e-3)
+
+
 # orbits the oracle reached from loops of its own chaotic runs, with the period the paper reports
 ORBITS = [("oracle_orbit_L39.json", 25.37),  # Fig. 5a
           ("oracle_orbit_L39_T76.json", 76.61)]  # Fig. 5c

@@ -244,6 +244,33 @@ def test_trajectory_plain64x128_imex(api):
     assert np.all(np.diff(Jh) <= 0)
 
 
+def test_log_plain64x128_20000_imex_steps(api):
+    """The 64 x 128 workload as specified: 20 000 IMEX steps at dtau = 5e-5 from its seed, J(tau)
+    and T(tau) every 10 steps against the oracle's stored log, to 1e-10, and the end state."""
+    g = json.load(open(os.path.join(HERE, "oracle_traj_plain64x128.json")))
+    spec = loopgen.config_loops(2)[0]
+    ud, Td = to_dev(spec.uhat[None], np.array([spec.T]))
+    every, n = g["log_every"], len(g["J_log"])
+    Jh = torch.zeros(g["steps"], 1, dtype=torch.float64, device=DEV)
+    Tl = torch.zeros(n, dtype=torch.float64, device=DEV)
+    ws = api.Workspace(api.workspace_bytes(spec.Nx, spec.Ns, 1))
+    for i in range(n):
+        Tl[i].copy_(Td[0])
+        api.loop_step(ud, Td, spec.L, g["dtau"], K.IMEX, every, J_hist=Jh[i * every:(i + 1) * every], ws=ws)
+    assert ws.status() == 0
+    J = Jh.cpu().numpy()[::every, 0]
+    Jo, To = np.array(g["J_log"]), np.array(g["T_log"])
+    assert np.max(np.abs(J - Jo) / Jo) <= 1e-10, np.max(np.abs(J - Jo) / Jo)
+    assert np.max(np.abs(Tl.cpu().numpy() - To) / To) <= 1e-10
+    assert abs(Td.item() - g["T_final"]) <= 1e-10 * g["T_final"]
+    assert abs(api.loop_cost(ud, Td, spec.L).item() - g["J_final"]) <= 1e-10 * g["J_final"]
+    uo = np.zeros_like(spec.uhat)
+    for j, k, re, im in g["uhat_final_band"]:
+        uo[k % spec.Ns, j] = complex(re, im)
+    assert relerr(ud.cpu().numpy()[0], uo, spec.Nx) < 1e-10
+    assert np.all(np.diff(Jh.cpu().numpy()[:, 0]) <= 0)
+
+
 @pytest.mark.parametrize("form", [0, 2])
 def test_reaches_the_oracle_converged_state(api, form):
     """Convergence parity: from the 32 x 32 workload's seed, IMEX at dtau = 0.05, the oracle
