@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_xA(Shape sh, Work w, const cd* __res
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_xB(Shape sh, Work w, const double* __restrict__ T,
                                                const cd* __restrict__ tw) {
-    extern __shared__ cd lds[];
+    extern __shared__ __align__(16) cd lds[];  // 16-byte aligned: one ds_read_b128 per complex value
     row_pass_X<M>(sh, blockIdx.x, w, T, lds, tw);
 }
 // one wavefront per loop: the row sums (in G) of loop blockIdx.x into J, dJ/dT (and T's update)
@@ -217,12 +217,9 @@ __global__ __launch_bounds__(256) void k_from_band(Shape sh, const cd* __restric
     const cd* s = src + (size_t)l * sh.C * sh.NB;
     for (int ty = ty0; ty < 32; ty += 8) {
         const int j = j0 + ty, e = e0 + tx;
-        cd v{0.0, 0.0};
-        if (j < sh.C && e < sh.N) {
-            const int kk = band_row(e, sh.N, sh.Ks);
-            if (kk >= 0) v = s[(size_t)j * sh.NB + kk];
-        }
-        tile[ty][tx] = v;
+        // a select of the loaded value (a local assigned in a branch would live in scratch)
+        const int kk = (j < sh.C && e < sh.N) ? band_row(e, sh.N, sh.Ks) : -1;
+        tile[ty][tx] = kk >= 0 ? s[(size_t)j * sh.NB + kk] : cd{0.0, 0.0};
     }
     __syncthreads();
     cd* o = out + (size_t)l * sh.N * sh.H;
@@ -552,7 +549,7 @@ __device__ __noinline__ void bk_E(const Shape& sh, int tile, const Work& w, doub
 }
 
 __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
-    extern __shared__ cd lds[];
+    extern __shared__ __align__(16) cd lds[];  // 16-byte aligned: one ds_read_b128 per complex value
     __shared__ double red[2 * kBlock / 64];
     __shared__ int s_item, s_stop;
     const int total = a.nA + a.nsteps * a.ips;
@@ -667,7 +664,7 @@ __device__ __forceinline__ void size_switch(int n, F&& f) {
 template <int PASS, int V>
 __global__ __launch_bounds__(kBlock) void k_rag(BatchArgs a, const uint32_t* __restrict__ codes, int s) {
     constexpr RagVariant var = rag_variant(PASS, V);
-    extern __shared__ cd lds[];
+    extern __shared__ __align__(16) cd lds[];  // 16-byte aligned: one ds_read_b128 per complex value
     __shared__ double red[2 * kBlock / 64];
     const uint32_t code = codes[blockIdx.x];
     const int l = (int)(code >> 16), tile = (int)(code & 0x1fff);
@@ -730,7 +727,7 @@ __global__ __launch_bounds__(kBlock, (ResG<M, N>::BLOCKS_PER_CU)) void k_residen
                                                      int scheme, int nsteps, double* J_hist, int* status,
                                                      const cd* __restrict__ tw) {
     using R = ResG<M, N>;
-    extern __shared__ cd lds[];
+    extern __shared__ __align__(16) cd lds[];  // 16-byte aligned: one ds_read_b128 per complex value
     cd* U = lds;
     cd* A = U + R::S;
     cd* X = A + R::W;
@@ -793,12 +790,8 @@ __global__ __launch_bounds__(kBlock, (ResG<M, N>::BLOCKS_PER_CU)) void k_residen
     cd* o = uout + (size_t)l * N * sh.H;
     for (int i = threadIdx.x; i < N * sh.H; i += kBlock) {
         const int e = i / sh.H, j = i % sh.H;
-        cd v{0.0, 0.0};
-        if (j < R::C) {
-            const int kk = band_row(e, N, R::Ks);
-            if (kk >= 0) v = U[j * R::NB + kk];
-        }
-        o[i] = v;
+        const int kk = j < R::C ? band_row(e, N, R::Ks) : -1;
+        o[i] = kk >= 0 ? U[j * R::NB + kk] : cd{0.0, 0.0};
     }
     if (threadIdx.x == 0) T[l] = sc[0];
 }
@@ -845,12 +838,8 @@ __global__ __launch_bounds__(256) void k_from_band_batch(const BatchLoop* loops,
     const cd* src = reinterpret_cast<const cd*>(ws + b.off.U);
     for (int ty = ty0; ty < 32; ty += 8) {
         const int j = j0 + ty, e = e0 + tx;
-        cd v{0.0, 0.0};
-        if (j < sh.C && e < sh.N) {
-            const int kk = band_row(e, sh.N, sh.Ks);
-            if (kk >= 0) v = src[(size_t)j * sh.NB + kk];
-        }
-        tile[ty][tx] = v;
+        const int kk = (j < sh.C && e < sh.N) ? band_row(e, sh.N, sh.Ks) : -1;
+        tile[ty][tx] = kk >= 0 ? src[(size_t)j * sh.NB + kk] : cd{0.0, 0.0};
     }
     __syncthreads();
     cd* o = pool + b.uoff;

@@ -398,30 +398,44 @@ struct RowG {
 // Load rows [g0, g0 + ROWS) of NT intermediates X[0..NT) into tiles tile + i * TILE, laid
 // out [j][r] with stride TS, coalesced along n. Rows past nrows read as zero. issue() puts
 // every global load of the tile in flight (into registers); commit() stores them to LDS, so
-// a caller can do other work while the loads travel. ROWS and N are powers of two.
+// a caller can do other work while the loads travel. ROWS and N are powers of two, and the
+// row passes' column count C = (M-1)/3 + 1 is CMAX. Tiles start at multiples of ROWS, so when
+// N >= ROWS a tile lies inside one loop and its elements sit at j N + r from the tile's first
+// row (32-bit offsets); shorter loops take the general row-by-row address.
 template <int ROWS, int CMAX, int TS, int TILE, int NT>
 struct RowTiles {
     static constexpr int NL = (ROWS * CMAX + kBlock - 1) / kBlock;
+    static constexpr int n = ROWS * CMAX;
     cd buf[NT][NL];
     __device__ __forceinline__ void issue(const cd* const (&X)[NT], size_t g0, const Shape& sh, size_t nrows) {
-        const int n = ROWS * sh.C;
+        if (sh.N >= ROWS) {
+            const size_t base = ((g0 >> sh.logN) * CMAX) * sh.N + (g0 & (size_t)(sh.N - 1));
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                const int i = threadIdx.x + k * kBlock;
+                const int j = i / ROWS, r = i % ROWS;
+                const bool ok = (n % kBlock == 0 || i < n) && g0 < nrows;
+#pragma unroll
+                for (int q = 0; q < NT; ++q) buf[q][k] = ok ? X[q][base + (j * sh.N + r)] : cd{0.0, 0.0};
+            }
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             const int i = threadIdx.x + k * kBlock;
             const int j = i / ROWS, r = i % ROWS;
             const size_t g = g0 + r;
             const bool ok = i < n && g < nrows;
-            const size_t off = ok ? ((g >> sh.logN) * sh.C + j) * sh.N + (g & (size_t)(sh.N - 1)) : 0;
+            const size_t off = ok ? ((g >> sh.logN) * CMAX + j) * sh.N + (g & (size_t)(sh.N - 1)) : 0;
 #pragma unroll
             for (int q = 0; q < NT; ++q) buf[q][k] = ok ? X[q][off] : cd{0.0, 0.0};
         }
     }
-    __device__ __forceinline__ void commit(cd* tile, const Shape& sh) const {
-        const int n = ROWS * sh.C;
+    __device__ __forceinline__ void commit(cd* tile, const Shape&) const {
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             const int i = threadIdx.x + k * kBlock;
-            if (i < n) {
+            if (n % kBlock == 0 || i < n) {
                 const int j = i / ROWS, r = i % ROWS;
 #pragma unroll
                 for (int q = 0; q < NT; ++q) tile[q * TILE + j * TS + r] = buf[q][k];
@@ -452,7 +466,7 @@ __device__ __forceinline__ void load_rows_lds(cd* tile, const cd* const (&X)[NT]
     static_assert(ROWS % 64 == 0, "a copy instruction covers 64 rows of one column");
     constexpr int RC = ROWS / 64;
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    const int per_field = sh.C * RC;
+    constexpr int per_field = CMAX * RC;
     const size_t g = g0 + lane;
     for (int k = wave; k < NT * per_field; k += kBlock / 64) {
         const int q = k / per_field, rem = k % per_field;
@@ -460,7 +474,7 @@ __device__ __forceinline__ void load_rows_lds(cd* tile, const cd* const (&X)[NT]
         cd* dst = tile + q * TILE + j * TS + r0;
         const size_t gr = g + r0;
         if (gr < nrows) {
-            const cd* src = X[q] + ((gr >> sh.logN) * sh.C + j) * sh.N + (gr & (size_t)(sh.N - 1));
+            const cd* src = X[q] + ((gr >> sh.logN) * CMAX + j) * sh.N + (gr & (size_t)(sh.N - 1));
             __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)const_cast<cd*>(src),
                                              (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
         } else {
@@ -470,18 +484,30 @@ __device__ __forceinline__ void load_rows_lds(cd* tile, const cd* const (&X)[NT]
     if constexpr (WAIT) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
+// Store tile[j][r] (stride TS) to rows [g0, g0 + ROWS) of X, addressed as RowTiles loads them.
 template <int ROWS, int CMAX>
 __device__ __forceinline__ void store_rows(const cd* tile, int TS, cd* X, size_t g0, const Shape& sh,
                                            size_t nrows) {
     constexpr int NL = (ROWS * CMAX + kBlock - 1) / kBlock;
-    const int n = ROWS * sh.C;
+    constexpr int n = ROWS * CMAX;
+    if (sh.N >= ROWS) {
+        if (g0 >= nrows) return;
+        cd* base = X + ((g0 >> sh.logN) * CMAX) * sh.N + (g0 & (size_t)(sh.N - 1));
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int i = threadIdx.x + k * kBlock;
+            const int j = i / ROWS, r = i % ROWS;
+            if (n % kBlock == 0 || i < n) base[j * sh.N + r] = tile[j * TS + r];
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
         const int i = threadIdx.x + k * kBlock;
         const int j = i / ROWS, r = i % ROWS;
         const size_t g = g0 + r;
         if (i < n && g < nrows)
-            X[((g >> sh.logN) * sh.C + j) * sh.N + (g & (size_t)(sh.N - 1))] = tile[j * TS + r];
+            X[((g >> sh.logN) * CMAX + j) * sh.N + (g & (size_t)(sh.N - 1))] = tile[j * TS + r];
     }
 }
 
@@ -573,7 +599,7 @@ __device__ __forceinline__ void row_forward_split(const Shape& sh, cd* va, cd* l
     wave_lds_sync();
     const int lane = threadIdx.x % 64;
     const int pw0 = (threadIdx.x / 64) * G::PW;
-    const int nout = 2 * G::PW * sh.C;
+    constexpr int nout = 2 * G::PW * G::CMAX;
     const double s = 0.5 / M;
     const double hq = (kTwoPi / sh.L) * (0.25 / M);  // q_j / 2 per unit j, with the 1/(2M) of the split
     cd outv[G::NOUT];
@@ -581,8 +607,8 @@ __device__ __forceinline__ void row_forward_split(const Shape& sh, cd* va, cd* l
     for (int i = 0; i < G::NOUT; ++i) {
         const int idx = lane + 64 * i;
         if (idx < nout) {
-            const int pp = pw0 + idx / (2 * sh.C);
-            const int rem = idx % (2 * sh.C);
+            const int pp = pw0 + idx / (2 * G::CMAX);
+            const int rem = idx % (2 * G::CMAX);
             const int j = rem >> 1;
             const cd* e2 = lds + pp * xlen<M>();
             const cd a = e2[xpos(j)];
@@ -600,8 +626,8 @@ __device__ __forceinline__ void row_forward_split(const Shape& sh, cd* va, cd* l
     for (int i = 0; i < G::NOUT; ++i) {
         const int idx = lane + 64 * i;
         if (idx < nout) {
-            const int pp = pw0 + idx / (2 * sh.C);
-            const int rem = idx % (2 * sh.C);
+            const int pp = pw0 + idx / (2 * G::CMAX);
+            const int rem = idx % (2 * G::CMAX);
             lds[(rem >> 1) * G::TS + ((rem & 1) ? G::P + pp : pp)] = outv[i];
         }
     }
