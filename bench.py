@@ -243,14 +243,6 @@ def main():
                 # the whole step, every pass, as the timed region ran it (its kernels may overlap)
                 "step_achieved": round(step_bytes / (e0.elapsed_time(e1) * 1e-3 / steps) / 1e9, 1),
                 "step_frac": round(step_bytes / (e0.elapsed_time(e1) * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS, 4)}
-    if tuning["schedule"] == "persistent":
-        # the timed region ran one persistent launch over all steps: that kernel is the one
-        gpu_s = e0.elapsed_time(e1) * 1e-3
-        achieved = step_bytes * steps / gpu_s / 1e9
-        roofline.update({"achieved": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
-                         "traffic": measured_traffic(args.workload, "k_batch"),
-                         "kernel": "k_batch (every pass of every step)", "bytes_per_launch": step_bytes * steps,
-                         "avg_launch_us": round(gpu_s * 1e6, 1)})
 
     # ---- plain method on the same loops: loop_step per loop, one after another
     plain = None

@@ -271,14 +271,15 @@ int loop_update(double L, int Nx, int Ns, int nloops, double* T, double* uhat,
  * loop_batch_step queues its kernels on `stream`, and allocates and synchronises nothing:
  * a conversion into band layout (which also makes every loop canonical), the steps (see
  * loop_batch_set_schedule), and the conversion back. Its work space
- * (loop_batch_info bytes) must be prepared once by loop_batch_workspace_init. After a
- * LOOP_EHANG status, prepare it again before reuse. */
+ * (loop_batch_info bytes) must be prepared once by loop_batch_workspace_init; a call that
+ * ended in LOOP_EHANG leaves it ready for the next call. */
 typedef enum { LOOP_BATCH_PER_PASS = 0, LOOP_BATCH_PERSISTENT = 1, LOOP_BATCH_STREAMS = 2 } loop_batch_schedule;
 int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns, void** plan);
 /* Choose how loop_batch_step runs the steps (results are identical bit for bit):
  *   LOOP_BATCH_PER_PASS (default): one kernel per pass over every loop's tiles, four per step;
  *   LOOP_BATCH_PERSISTENT: one launch for all steps, blocks pulling (pass, loop, tile) items
- *   in dependency order (see the scheduler notes in the source);
+ *   in dependency order (see the scheduler notes in the source); it measured 3-5x slower than
+ *   the other two, and loop_batch_autotune does not choose it;
  *   LOOP_BATCH_STREAMS: the loops split into K groups of about equal work (K from
  *   loop_batch_set_streams, 2 to 4, default 2), group 0 on `stream` and the others on streams
  *   the plan owns (default priority), each started one pass after the previous group, so that
@@ -288,6 +289,11 @@ int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns,
  *   overlap (the plan's streams and events are shared). */
 int loop_batch_set_schedule(void* plan, int schedule);
 int loop_batch_set_streams(void* plan, int nstreams);
+/* Bound, in seconds, of one dependency wait of the persistent schedule (default 2; 0 to 3600).
+ * A wait that runs out abandons the launch: every block leaves at its next wait, the status
+ * word becomes LOOP_EHANG, and the state the call leaves behind is not a step. The counters
+ * the schedule uses are cleared before each launch, so the next call runs normally. */
+int loop_batch_set_wait_limit(void* plan, double seconds);
 int loop_batch_destroy(void* plan);
 int loop_batch_info(const void* plan, size_t* ws_bytes, size_t* pool_elems, long long* uhat_offsets);
 int loop_batch_workspace_init(const void* plan, void* ws, size_t ws_bytes, void* stream);
@@ -335,16 +341,17 @@ int loop_batch_store(const void* plan, double* uhat_pool, void* ws, size_t ws_by
  * loop_batch_step; neither is modified), every usable variant of every pass over `reps`
  * back-to-back launches (best of three trials, hipEvent timing on `stream`), keeps the
  * fastest per pass (the plan's current variant unless another is faster by more than 1%),
- * then times `reps` whole steps of each schedule (the multi-stream one with
- * 2, 3 and 4 streams) and keeps the fastest. The work of every kernel is independent of dtau
+ * then times `reps` whole steps of the per-pass schedule and of the multi-stream one with 2, 3
+ * and 4 streams, and keeps the fastest (the persistent schedule is not timed; its entry in the
+ * report is -1). The work of every kernel is independent of dtau
  * and scheme, so the timing runs use a step of 1e-30 (IMEX), which leaves the state unchanged
  * to the last bit in practice and keeps every repetition finite. It allocates temporary
  * device copies of T and the pool, synchronises `stream`, and overwrites the work space's
  * intermediates (the work space stays prepared). reps in [1, 1000]. report, if not NULL,
  * receives 5 * LOOP_BATCH_VARIANTS + 5 doubles: the mean microseconds per launch of (pass,
  * variant) at index pass * LOOP_BATCH_VARIANTS + variant (-1 for variants not usable), then
- * microseconds per step of the per-pass, the persistent, and the multi-stream schedule with
- * 2, 3 and 4 streams. Returns a device status raised while timing, else LOOP_OK. */
+ * microseconds per step of the per-pass, the persistent (-1, not timed), and the
+ * multi-stream schedule with 2, 3 and 4 streams. Returns a device status raised while timing, else LOOP_OK. */
 #define LOOP_BATCH_VARIANTS 4
 int loop_batch_set_variant(void* plan, int pass, int variant);
 int loop_batch_get_config(const void* plan, int* schedule, int* variants, int* nstreams);

@@ -29,7 +29,7 @@ EXPORTS = [
     "loop_cost", "loop_adjoint_grad", "loop_cost_grad", "loop_to_band", "loop_from_band", "loop_cost_fwd",
     "loop_cost_bwd", "loop_update_grad", "loop_step", "loop_step_noalloc", "loop_set_resident",
     "loop_resident_supported", "loop_step_form", "loop_extrapolate", "loop_converge", "loop_step_xi",
-    "loop_step_xi_workspace_bytes", "loop_expanded_grad", "loop_step_expanded", "loop_update", "loop_batch_create", "loop_batch_set_schedule", "loop_batch_set_streams",
+    "loop_step_xi_workspace_bytes", "loop_expanded_grad", "loop_step_expanded", "loop_update", "loop_batch_create", "loop_batch_set_schedule", "loop_batch_set_streams", "loop_batch_set_wait_limit",
     "loop_batch_destroy",
     "loop_batch_info", "loop_batch_workspace_init", "loop_batch_step", "loop_batch_load", "loop_batch_pass",
     "loop_batch_store", "loop_batch_set_variant", "loop_batch_get_config", "loop_batch_autotune",
@@ -83,6 +83,7 @@ _SIGS = {
                        ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_i), ctypes.POINTER(_d), _p, _sz, _p], _i),
     "loop_batch_set_schedule": ([_p, _i], _i),
     "loop_batch_set_streams": ([_p, _i], _i),
+    "loop_batch_set_wait_limit": ([_p, _d], _i),
     "loop_batch_destroy": ([_p], _i),
     "loop_batch_info": ([_p, ctypes.POINTER(_sz), ctypes.POINTER(_sz), ctypes.POINTER(ctypes.c_longlong)], _i),
     "loop_batch_workspace_init": ([_p, _p, _sz, _p], _i),

@@ -398,6 +398,10 @@ class Batch:
         if nstreams is not None:
             check(_lib.lib().loop_batch_set_streams(self._plan, int(nstreams)), "loop_batch_set_streams")
 
+    def set_wait_limit(self, seconds: float):
+        """Bound of one dependency wait of the persistent schedule (see loop_batch_set_wait_limit)."""
+        check(_lib.lib().loop_batch_set_wait_limit(self._plan, float(seconds)), "loop_batch_set_wait_limit")
+
     VARIANTS = 4
     PASS_NAMES = ("A", "B", "C", "D", "E")
 
@@ -431,7 +435,8 @@ class Batch:
         out = self.config()
         out["pass_us"] = passes
         names = ("per-pass", "persistent", "streams-2", "streams-3", "streams-4")
-        out["step_us"] = {name: round(rep[5 * self.VARIANTS + i], 3) for i, name in enumerate(names)}
+        out["step_us"] = {name: round(rep[5 * self.VARIANTS + i], 3) for i, name in enumerate(names)
+                          if rep[5 * self.VARIANTS + i] >= 0}
         return out
 
     def _check_state(self, pool, T):
@@ -483,7 +488,7 @@ class Batch:
         return int(_lib.lib().loop_status_sync(_ptr(self.ws), _stream_ptr()))
 
     def reset(self):
-        """Prepare the work space again (needed after a LOOP_EHANG status)."""
+        """Prepare the work space again (clears the sticky status and the schedule counters)."""
         check(_lib.lib().loop_batch_workspace_init(self._plan, _ptr(self.ws), self.ws.numel(), _stream_ptr()),
               "loop_batch_workspace_init")
 

@@ -433,9 +433,9 @@ __global__ void k_copy_status(const WsHeader* h, int* status) { *status = h->sta
 // if one runs out, the block raises an abort flag that every other wait also checks, the
 // status becomes LOOP_EHANG, and all blocks leave.
 //
-// Completion counters live in the work space. The block that finishes a loop's last item
-// resets that loop's counter, and the last block to leave resets the item counter. A
-// work space is therefore ready for the next launch on the same stream.
+// The queue and completion counters live in the work space and are cleared by a small kernel
+// queued before every launch (k_batch_reset), so that a launch abandoned after a wait ran out
+// leaves nothing behind for the next one.
 struct WsOff {  // byte offsets of one loop's regions inside the work space
     size_t A, BD, Cb, U, G, partial, J, dJdT, Told;
 };
@@ -474,9 +474,11 @@ struct BatchArgs {
     double dtau;
     int scheme;
     const cd* tw;
+    unsigned long long spin_ticks;  // bound of one dependency wait, in ticks of the 100 MHz clock
 };
 
-constexpr uint64_t kSpinTicks = 200000000ull;  // 2 s of the 100 MHz constant clock
+constexpr double kWallClockHz = 1e8;       // wall_clock64() runs at 100 MHz
+constexpr double kDefaultWaitLimit = 2.0;  // seconds
 
 __device__ __forceinline__ Work batch_work(const BatchLoop& b, char* ws, int* status) {
     Work w{};
@@ -493,15 +495,17 @@ __device__ __forceinline__ Work batch_work(const BatchLoop& b, char* ws, int* st
     return w;
 }
 
-// Wait until *cnt >= target. Returns 1 when the launch is being abandoned.
-__device__ int wait_count(int* cnt, int target, BatchQueue* q, int* status) {
+// Wait until *cnt >= target. Returns 1 when the launch is being abandoned: this wait ran out
+// (it raises the abort flag), or another one did. Either way the status word says LOOP_EHANG,
+// so that an abandoned launch never passes for a complete one.
+__device__ int wait_count(int* cnt, int target, BatchQueue* q, int* status, unsigned long long spin_ticks) {
     if (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) return 0;
     const uint64_t t0 = wall_clock64();
     for (;;) {
         __builtin_amdgcn_s_sleep(2);
         if (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) return 0;
-        if (__hip_atomic_load(&q->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 1;
-        if (wall_clock64() - t0 > kSpinTicks) {
+        if (__hip_atomic_load(&q->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+            wall_clock64() - t0 > spin_ticks) {
             atomicExch(&q->abort, 1);
             atomicCAS(status, 0, LOOP_EHANG);
             return 1;
@@ -575,7 +579,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
         }
         // Thread 0's acquiring load of the counter invalidates this CU's L1 and this XCD's L2,
         // so the block's loads after the barrier see the producers' written-back results.
-        if (threadIdx.x == 0) s_stop = wait_count(&a.done[l], target, a.q, a.status);
+        if (threadIdx.x == 0) s_stop = wait_count(&a.done[l], target, a.q, a.status, a.spin_ticks);
         __syncthreads();
         if (s_stop) break;
         const Work w = batch_work(b, a.ws, a.status);
@@ -606,14 +610,22 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
         __syncthreads();
         if (threadIdx.x == 0) {
             __threadfence();
-            const int need = b.nt[PASS_A] + a.nsteps * b.ipl;
-            if (atomicAdd(&a.done[l], 1) + 1 == need) atomicExch(&a.done[l], 0);
+            atomicAdd(&a.done[l], 1);
         }
     }
-    if (threadIdx.x == 0 && atomicAdd(&a.q->exited, 1) == (int)gridDim.x - 1) {
-        atomicExch(&a.q->next, 0);
-        atomicExch(&a.q->exited, 0);
+}
+
+// Queue and completion counters of the persistent schedule, cleared before every launch (a
+// kernel rather than a memset, so that the step can be recorded into a graph and replayed):
+// a launch abandoned after a wait ran out leaves them partly counted.
+__global__ void k_batch_reset(BatchQueue* q, int* done, int nloops) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        q->next = 0;
+        q->exited = 0;
+        q->abort = 0;
     }
+    for (int l = i; l < nloops; l += gridDim.x * blockDim.x) done[l] = 0;
 }
 
 // Launch-per-pass form of the same batched step: one kernel per pass covers the tiles of
@@ -1376,7 +1388,8 @@ struct BatchPlan {
     int grid = 1;
     uint32_t* d_pass_codes = nullptr;  // all loops' tiles, pass by pass (A, B, C, D, E)
     int pass_off[6] = {0, 0, 0, 0, 0, 0};
-    int schedule = 0;                  // LOOP_BATCH_PER_PASS or LOOP_BATCH_PERSISTENT
+    int schedule = 0;                  // LOOP_BATCH_PER_PASS, LOOP_BATCH_PERSISTENT or LOOP_BATCH_STREAMS
+    double wait_limit = kDefaultWaitLimit;  // seconds: bound of one dependency wait (persistent)
     int variant[5] = {0, 0, 0, 0, 0};  // k_rag variant of each pass
     size_t pass_lds[5][kRagVariants] = {};  // dynamic LDS of each pass's launches, per variant
     int min_m = 1 << 30, max_m = 0, min_n = 1 << 30, max_n2 = 0;  // transform sizes present
@@ -2226,6 +2239,7 @@ BatchArgs batch_args(const BatchPlan* p, char* base, double* T, double* J_hist, 
     a.dtau = dtau;
     a.scheme = scheme;
     a.tw = tw;
+    a.spin_ticks = (unsigned long long)(p->wait_limit * kWallClockHz);
     return a;
 }
 
@@ -2353,6 +2367,7 @@ int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau,
         if (p->schedule == LOOP_BATCH_PERSISTENT) {
             const long long total = (long long)p->nA + (long long)nsteps * p->ips;
             if (total >= (1ll << 31)) return LOOP_EINVAL;
+            hipLaunchKernelGGL(k_batch_reset, dim3((p->nloops + 255) / 256), dim3(256), 0, hs, a.q, a.done, p->nloops);
             TraceScope ts_("k_batch", 0, hs);
             hipLaunchKernelGGL(k_batch, dim3(p->grid), dim3(kBlock), p->lds_bytes, hs, a);
         } else if (p->schedule == LOOP_BATCH_STREAMS) {
@@ -2364,6 +2379,13 @@ int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau,
         }
     }
     return loop_batch_store(plan, uhat_pool, ws, ws_bytes, stream);
+}
+
+int loop_batch_set_wait_limit(void* plan, double seconds) {
+    BatchPlan* p = static_cast<BatchPlan*>(plan);
+    if (!p || !(seconds >= 0.0) || !(seconds <= 3600.0)) return LOOP_EINVAL;
+    p->wait_limit = seconds;
+    return LOOP_OK;
 }
 
 int loop_batch_set_streams(void* plan, int nstreams) {
@@ -2463,10 +2485,13 @@ int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, in
         if (best_v != incumbent && t_inc > 0.0 && best_t > 0.99 * t_inc) best_v = incumbent;
         p->variant[pass] = best_v;
     }
-    // schedules: per-pass, persistent, then the multi-stream one with 2, 3 and 4 streams
+    // schedules: per-pass, then the multi-stream one with 2, 3 and 4 streams. The persistent
+    // schedule is not timed: it measured 3-5x slower than these on every workload (an
+    // agent-scope release per item to order work across the XCDs' separate L2 caches).
     double best_us = 1e300;
     int best_s = LOOP_BATCH_PER_PASS, best_k = 2;
     for (int c = 0; c < 5; ++c) {
+        if (c == 1) continue;  // persistent: reported as -1
         const int sc = c < 2 ? c : LOOP_BATCH_STREAMS, k = c < 2 ? 2 : c;
         p->schedule = sc;
         p->nstreams = k;
