@@ -174,6 +174,20 @@ __device__ __forceinline__ ColPos col_pos(const Shape& sh, int block) {
     return p;
 }
 
+// The band values of this thread's slots of column (l, j) (zero outside the band or for an
+// inactive column), read through band_get. Column passes issue these loads before their
+// transforms, so that their latency overlaps the transform instead of following it.
+template <int N>
+__device__ __forceinline__ void band_prefetch(const Shape& sh, const ColPos& p, const cd* u, int herm0,
+                                              cd* out) {
+    using G = ColG<N>;
+#pragma unroll
+    for (int m = 0; m < G::PT; ++m) {
+        const int kk = band_row(p.t + m * G::TPF, N, sh.Ks);
+        out[m] = (p.active && kk >= 0) ? band_get(u, p.j, kk, sh.NB, herm0) : cd{0.0, 0.0};
+    }
+}
+
 // Inverse s-transform of band column values v (already zero outside the band) into X.
 template <int N>
 __device__ __forceinline__ void col_inverse_store(const Shape& sh, const ColPos& p, cd* v, cd* X, cd* ex,
@@ -217,23 +231,12 @@ __device__ __forceinline__ void col_pass_AC(const Shape& sh, int block, const Wo
     const cd* u = w.U + col * sh.NB;
     const cd* r = w.R + col * sh.NB;
     const double q = kTwoPi * p.j / sh.L;
-    cd v[G::PT];
-#pragma unroll
-    for (int m = 0; m < G::PT; ++m) {
-        const int kk = band_row(p.t + m * G::TPF, N, sh.Ks);
-        v[m] = (p.active && kk >= 0) ? band_get(u, p.j, kk, sh.NB, w.herm0) : cd{0.0, 0.0};
-    }
+    cd v[G::PT], rv[G::PT];
+    band_prefetch<N>(sh, p, u, w.herm0, v);
+    band_prefetch<N>(sh, p, r, 0, rv);  // in flight during the first transform
     col_inverse_store<N>(sh, p, v, w.A, ex, twc);
 #pragma unroll
-    for (int m = 0; m < G::PT; ++m) {
-        const int kk = band_row(p.t + m * G::TPF, N, sh.Ks);
-        cd x{0.0, 0.0};
-        if (p.active && kk >= 0) {
-            const cd rr = r[kk];
-            x = cd{-q * rr.y, q * rr.x};  // i q r
-        }
-        v[m] = x;
-    }
+    for (int m = 0; m < G::PT; ++m) v[m] = cd{-q * rv[m].y, q * rv[m].x};  // i q r (zero outside the band)
     col_inverse_store<N>(sh, p, v, w.Cb, ex, twc);
 }
 
@@ -245,9 +248,10 @@ __device__ __forceinline__ void col_pass_C(const Shape& sh, int block, const dou
     const ColPos p = col_pos<N>(sh, block);
     const size_t col = (size_t)p.l * sh.C + p.j;
     const cd* Bc = w.BD + col * N;
-    cd v[G::PT];
+    cd v[G::PT], ub[G::PT];
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) v[m] = p.active ? Bc[p.t + m * G::TPF] : cd{0.0, 0.0};
+    band_prefetch<N>(sh, p, w.U + col * sh.NB, w.herm0, ub);  // in flight during the transform
     TwCache<N, G::PT> twc;
     tw_cache_load<N, G::PT>(twc, p.t, tw);
     fft<N, G::PT, false>(v, p.t, ex + p.f * xlen<N>(), twc);
@@ -260,7 +264,6 @@ __device__ __forceinline__ void col_pass_C(const Shape& sh, int block, const dou
     const double invN = 1.0 / N;
     const double wj = (p.j == 0) ? 1.0 : 2.0;
     double Jp = 0.0, dTp = 0.0;
-    const cd* u = w.U + col * sh.NB;
     cd* g = w.G + col * sh.NB;
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) {
@@ -271,7 +274,7 @@ __device__ __forceinline__ void col_pass_C(const Shape& sh, int block, const dou
             const int k = (e < N / 2) ? e : e - N;
             const double om = kTwoPi * k;
             const cd wh = cscale(v[m], invN);  // (u u_x)_hat
-            const cd uu = band_get(u, p.j, kk, sh.NB, w.herm0);
+            const cd uu = ub[m];
             const double a = om * invT;
             // r = -(i om/T) u - (u u_x)_hat + (q^2 - q^4) u
             cd r;
@@ -313,9 +316,11 @@ __device__ __forceinline__ void col_pass_E(const Shape& sh, int block, const Wor
     const ColPos p = col_pos<N>(sh, block);
     const size_t col = (size_t)p.l * sh.C + p.j;
     const cd* Dc = w.BD + col * N;
-    cd v[G::PT];
+    cd v[G::PT], gb[G::PT];
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) v[m] = p.active ? Dc[p.t + m * G::TPF] : cd{0.0, 0.0};
+    // G_lin, U1 or (reverse mode) the saved residual, in flight during the transform
+    band_prefetch<N>(sh, p, (mode == MODE_ADJOINT ? w.R : w.G) + col * sh.NB, 0, gb);
     TwCache<N, G::PT> twc;
     tw_cache_load<N, G::PT>(twc, p.t, tw);
     fft<N, G::PT, false>(v, p.t, ex + p.f * xlen<N>(), twc);
@@ -331,7 +336,6 @@ __device__ __forceinline__ void col_pass_E(const Shape& sh, int block, const Wor
                                                          : 1.0;
     cd* g = w.G + col * sh.NB;
     cd* u = w.U + col * sh.NB;
-    const cd* r = w.R + col * sh.NB;
     if (mode == MODE_ADJOINT && w.grad_T && p.active && p.j == 0 && p.t == 0)
         w.grad_T[p.l] = (w.gJ ? w.gJ[p.l] : 1.0) * w.dJdT_in[p.l];
 #pragma unroll
@@ -343,7 +347,7 @@ __device__ __forceinline__ void col_pass_E(const Shape& sh, int block, const Wor
             const cd ph = cscale(v[m], invN);  // (u r_x)_hat
             if (mode == MODE_ADJOINT) {
                 // G_lin = (-i om/T - q^2 + q^4) r, as pass C forms it, then G_1 = G_lin - p_hat
-                const cd rr = r[kk];
+                const cd rr = gb[m];
                 const int k = (e < N / 2) ? e : e - N;
                 const double a = kTwoPi * k * (1.0 / Tl);
                 cd gl;
@@ -354,7 +358,7 @@ __device__ __forceinline__ void col_pass_E(const Shape& sh, int block, const Wor
                 v[m] = x;
                 continue;
             }
-            const cd gg = g[kk];
+            const cd gg = gb[m];
             if (mode == MODE_STEP) {
                 double sig = 1.0;
                 if (scheme) {
