@@ -113,23 +113,31 @@ int loop_cost_grad(double L, int Nx, int Ns, int nloops, const double* T, const 
  * eq. KS_L_dagger, App. B). The forward evaluates J = 1/2 int int r^2 and dJ/dT (each nloops,
  * dJdT may be NULL) and leaves the residual r_hat in `rsave` (band layout, nloops x C x NB
  * complex, caller-owned): the state-sized quantity the reverse pass needs. The reverse pass
- * recomputes u on the grid from u_hat, forms r_x from the saved residual and applies the
- * adjoint operator, G_1 = -(1/T) r_s - u r_x + r_xx + r_xxxx (eq. KS_G); none of the forward's
- * transform intermediates is stored. It writes the gradient of sum_l gJ[l] J_l in the complex
- * convention dJ/dRe + i dJ/dIm, in the layout of u:
+ * forms r_x from the saved residual, needs u on the grid, and applies the adjoint operator,
+ * G_1 = -(1/T) r_s - u r_x + r_xx + r_xxxx (eq. KS_G). It writes the gradient of
+ * sum_l gJ[l] J_l in the complex convention dJ/dRe + i dJ/dIm, in the layout of u:
  *   grad_u = -gJ[l] w_j L G_1 in the band (w_0 = 1, w_j = 2 for j >= 1), 0 elsewhere,
  *   grad_T[l] = gJ[l] dJdT[l] (dJdT from the forward; grad_T may be NULL),
  * gJ may be NULL (all ones). The results equal loop_adjoint_grad's G_1 (scaled) bit for bit.
- * `layout` is LOOP_LAYOUT_RFFT or LOOP_LAYOUT_BAND for u and grad_u. rsave must not alias u;
- * grad_u must alias neither u nor rsave. Work space: loop_workspace_bytes. */
+ * `usave` trades memory for work. NULL: the reverse pass recomputes u on the grid from u_hat
+ * (one more inverse s-transform per column) and stores nothing grid-sized. Otherwise a
+ * caller-owned buffer of nloops x C x Ns complex values ([l][j][n]: the x-coefficient j of u at
+ * s-grid point n, i.e. the forward's inverse s-transform of each retained column) that the
+ * forward fills and the reverse pass reads in place of recomputing it; pass the same buffer,
+ * unchanged, to the reverse pass of the same u (the results are bitwise those without it).
+ * With usave the reverse pass does not read u.
+ * `layout` is LOOP_LAYOUT_RFFT or LOOP_LAYOUT_BAND for u and grad_u. rsave and usave must not
+ * alias u or each other; grad_u must alias none of u, rsave, usave. Work space:
+ * loop_workspace_bytes. */
 typedef enum { LOOP_LAYOUT_RFFT = 0, LOOP_LAYOUT_BAND = 1 } loop_layout;
 int loop_to_band(int Nx, int Ns, int nloops, const double* uhat, double* uband, void* stream);
 int loop_from_band(int Nx, int Ns, int nloops, const double* uband, double* uhat, void* stream);
 int loop_cost_fwd(double L, int Nx, int Ns, int nloops, int layout, const double* T, const double* u,
-                  double* J, double* dJdT, double* rsave, void* ws, size_t ws_bytes, void* stream);
+                  double* J, double* dJdT, double* rsave, double* usave, void* ws, size_t ws_bytes,
+                  void* stream);
 int loop_cost_bwd(double L, int Nx, int Ns, int nloops, int layout, const double* T, const double* u,
-                  const double* rsave, const double* dJdT, const double* gJ, double* grad_u,
-                  double* grad_T, void* ws, size_t ws_bytes, void* stream);
+                  const double* rsave, const double* usave, const double* dJdT, const double* gJ,
+                  double* grad_u, double* grad_T, void* ws, size_t ws_bytes, void* stream);
 
 /* The fictitious-time update of Sec. 4.2 from the gradient of sum_l J_l (gJ = 1) in the
  * convention above, in one kernel per array: G_1 = -grad_u / (w_j L) in the band, then

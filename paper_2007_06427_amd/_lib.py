@@ -63,8 +63,8 @@ _SIGS = {
     "loop_cost_grad": ([_d, _i, _i, _i, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
     "loop_to_band": ([_i, _i, _i, _p, _p, _p], _i),
     "loop_from_band": ([_i, _i, _i, _p, _p, _p], _i),
-    "loop_cost_fwd": ([_d, _i, _i, _i, _i, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
-    "loop_cost_bwd": ([_d, _i, _i, _i, _i, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
+    "loop_cost_fwd": ([_d, _i, _i, _i, _i, _p, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
+    "loop_cost_bwd": ([_d, _i, _i, _i, _i, _p, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p], _i),
     "loop_update_grad": ([_d, _i, _i, _i, _i, _p, _p, _p, _p, _d, _i, _p], _i),
     "loop_step": ([_d, _i, _i, _i, _p, _p, _d, _i, _i, _p, _p, _sz, _p], _i),
     "loop_step_noalloc": ([_d, _i, _i, _i, _p, _p, _d, _i, _i, _p, _p, _p], _i),

@@ -179,34 +179,56 @@ def _layout_of(u: torch.Tensor, layout: int, grid):
     return band_shape_of(u, Nx, Ns), int(Nx), int(Ns)
 
 
-def loop_cost_fwd(u: torch.Tensor, T, L: float, layout: int = LAYOUT_RFFT, grid=None, ws: Workspace = None):
+def saved_u(nloops: int, Nx: int, Ns: int, device) -> torch.Tensor:
+    """An empty buffer for the forward's u on the s grid (nloops, C, Ns) complex128, the
+    `usave` of loop_cost_fwd / loop_cost_bwd."""
+    C, _ = band_dims(Nx, Ns)
+    return torch.empty((nloops, C, Ns), dtype=torch.complex128, device=device)
+
+
+def _check_usave(usave, nl, Nx, Ns, device):
+    if usave is None:
+        return None
+    C, _ = band_dims(Nx, Ns)
+    if (usave.shape != (nl, C, Ns) or usave.dtype != torch.complex128 or not usave.is_contiguous()
+            or usave.device != device):
+        raise ValueError(f"usave must be a contiguous complex128 tensor of shape {(nl, C, Ns)} on {device}")
+    return _ptr(usave)
+
+
+def loop_cost_fwd(u: torch.Tensor, T, L: float, layout: int = LAYOUT_RFFT, grid=None, ws: Workspace = None,
+                  usave: torch.Tensor = None):
     """Forward pass of the cost: (J, dJ/dT, rsave), rsave the band residual the reverse pass
-    takes. `grid` = (Nx, Ns) for the band layout."""
+    takes. `grid` = (Nx, Ns) for the band layout. usave (see saved_u), if given, receives u on
+    the s grid for the reverse pass."""
     nl, Nx, Ns = _layout_of(u, layout, grid)
     T = _periods(T, nl, u.device)
     C, NB = band_dims(Nx, Ns)
     J = torch.empty(nl, dtype=torch.float64, device=u.device)
     dJdT = torch.empty(nl, dtype=torch.float64, device=u.device)
     rsave = torch.empty((nl, C, NB), dtype=torch.complex128, device=u.device)
+    us = _check_usave(usave, nl, Nx, Ns, u.device)
     ws = ws or workspace(Nx, Ns, nl)
     check(_lib.lib().loop_cost_fwd(float(L), Nx, Ns, nl, int(layout), _ptr(T), _ptr(u), _ptr(J), _ptr(dJdT),
-                                   _ptr(rsave), ws.ptr, ws.nbytes, _stream_ptr()), "loop_cost_fwd")
+                                   _ptr(rsave), us, ws.ptr, ws.nbytes, _stream_ptr()), "loop_cost_fwd")
     return J, dJdT, rsave
 
 
 def loop_cost_bwd(u: torch.Tensor, T, L: float, rsave: torch.Tensor, dJdT: torch.Tensor, gJ: torch.Tensor = None,
-                  layout: int = LAYOUT_RFFT, grid=None, ws: Workspace = None):
-    """Reverse pass from the forward's saved residual: (grad_u, grad_T) of sum_l gJ[l] J_l."""
+                  layout: int = LAYOUT_RFFT, grid=None, ws: Workspace = None, usave: torch.Tensor = None):
+    """Reverse pass from the forward's saved residual: (grad_u, grad_T) of sum_l gJ[l] J_l.
+    usave: the buffer the forward of the same u filled, or None to recompute u on the grid."""
     nl, Nx, Ns = _layout_of(u, layout, grid)
     T = _periods(T, nl, u.device)
     if gJ is not None and (gJ.dtype != torch.float64 or gJ.numel() != nl or not gJ.is_contiguous()):
         raise ValueError("gJ must be a contiguous float64 tensor with one entry per loop")
+    us = _check_usave(usave, nl, Nx, Ns, u.device)
     gu = torch.empty_like(u)
     gT = torch.empty(nl, dtype=torch.float64, device=u.device)
     ws = ws or workspace(Nx, Ns, nl)
-    check(_lib.lib().loop_cost_bwd(float(L), Nx, Ns, nl, int(layout), _ptr(T), _ptr(u), _ptr(rsave), _ptr(dJdT),
-                                   _ptr(gJ) if gJ is not None else None, _ptr(gu), _ptr(gT), ws.ptr, ws.nbytes,
-                                   _stream_ptr()), "loop_cost_bwd")
+    check(_lib.lib().loop_cost_bwd(float(L), Nx, Ns, nl, int(layout), _ptr(T), _ptr(u), _ptr(rsave), us,
+                                   _ptr(dJdT), _ptr(gJ) if gJ is not None else None, _ptr(gu), _ptr(gT), ws.ptr,
+                                   ws.nbytes, _stream_ptr()), "loop_cost_bwd")
     return gu, gT
 
 

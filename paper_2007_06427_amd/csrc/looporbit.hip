@@ -75,6 +75,13 @@ __global__ __launch_bounds__(kBlock) void k_colAC(Shape sh, Work w, const cd* __
     col_pass_AC<N>(sh, blockIdx.x, w, ex, tw);
 }
 
+// the residual half of k_colAC, for a reverse pass given u on the s grid
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_colR(Shape sh, Work w, const cd* __restrict__ tw) {
+    __shared__ cd ex[ColG<N>::LDS];
+    col_pass_AC<N, false>(sh, blockIdx.x, w, ex, tw);
+}
+
 // one wavefront per loop
 __global__ __launch_bounds__(64) void k_finalize(Shape sh, Work w, double* T, double* Jout, double* dJdTout) {
     finalize_loop(sh, blockIdx.x, w, T, MODE_COST, 0.0, nullptr, Jout, dJdTout);
@@ -1172,7 +1179,12 @@ int launch_E(const Shape& s, const Work& w, int mode, double dtau, int scheme, i
         default: return LOOP_EINVAL;
     }
 }
-int launch_AC(const Shape& s, const Work& w, const cd* tw, hipStream_t st) {
+int launch_AC(const Shape& s, const Work& w, const cd* tw, hipStream_t st, bool with_u) {
+    if (!with_u) {
+        LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colR", S_, st);
+                       hipLaunchKernelGGL(k_colR<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
+        return LOOP_OK;
+    }
     LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colAC", S_, st);
                    hipLaunchKernelGGL(k_colAC<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
     return LOOP_OK;
@@ -1686,19 +1698,20 @@ int bind_state(const Shape& s, Work& w, int layout, const double* u, hipStream_t
 }  // namespace
 
 int loop_cost_fwd(double L, int Nx, int Ns, int nloops, int layout, const double* T, const double* u, double* J,
-                  double* dJdT, double* rsave, void* ws, size_t ws_bytes, void* stream) {
+                  double* dJdT, double* rsave, double* usave, void* ws, size_t ws_bytes, void* stream) {
     Shape s;
     Work w;
     const cd* tw;
     if (layout != LOOP_LAYOUT_RFFT && layout != LOOP_LAYOUT_BAND) return LOOP_EINVAL;
     if (!aligned(T, 8) || !aligned(u, 16) || !aligned(J, 8) || !aligned(rsave, 16) || (dJdT && !aligned(dJdT, 8)) ||
-        (const void*)u == (const void*)rsave)
+        (const void*)u == (const void*)rsave || (usave && (!aligned(usave, 16) || usave == rsave || usave == u)))
         return LOOP_EINVAL;
     int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
     if (st) return st;
     hipStream_t hs = (hipStream_t)stream;
     if ((st = bind_state(s, w, layout, u, hs))) return st;
     w.G = reinterpret_cast<cd*>(rsave);  // pass C writes the residual there
+    if (usave) w.A = reinterpret_cast<cd*>(usave);  // pass A leaves u on the s grid there
     if ((st = launch_A(s, w, tw, hs))) return st;
     if ((st = launch_B(s, w, tw, hs))) return st;
     if ((st = launch_C(s, T, w, MODE_RESIDUAL, 0.0, 0, tw, hs))) return st;
@@ -1710,27 +1723,30 @@ int loop_cost_fwd(double L, int Nx, int Ns, int nloops, int layout, const double
 }
 
 int loop_cost_bwd(double L, int Nx, int Ns, int nloops, int layout, const double* T, const double* u,
-                  const double* rsave, const double* dJdT, const double* gJ, double* grad_u, double* grad_T, void* ws,
-                  size_t ws_bytes, void* stream) {
+                  const double* rsave, const double* usave, const double* dJdT, const double* gJ, double* grad_u,
+                  double* grad_T, void* ws, size_t ws_bytes, void* stream) {
     Shape s;
     Work w;
     const cd* tw;
     if (layout != LOOP_LAYOUT_RFFT && layout != LOOP_LAYOUT_BAND) return LOOP_EINVAL;
     if (!aligned(T, 8) || !aligned(u, 16) || !aligned(rsave, 16) || !aligned(grad_u, 16) || (gJ && !aligned(gJ, 8)) ||
-        (const void*)grad_u == (const void*)u || (const void*)grad_u == (const void*)rsave)
+        (const void*)grad_u == (const void*)u || (const void*)grad_u == (const void*)rsave ||
+        (usave && (!aligned(usave, 16) || (const void*)grad_u == (const void*)usave)))
         return LOOP_EINVAL;
     if (grad_T && (!aligned(grad_T, 8) || !aligned(dJdT, 8))) return LOOP_EINVAL;
     int st = prepare(L, Nx, Ns, nloops, ws, ws_bytes, &s, &w, &tw);
     if (st) return st;
     hipStream_t hs = (hipStream_t)stream;
-    if ((st = bind_state(s, w, layout, u, hs))) return st;
+    // the spectrum itself is read only to recompute u on the s grid
+    if (!usave && (st = bind_state(s, w, layout, u, hs))) return st;
     w.R = reinterpret_cast<const cd*>(rsave);
     w.gJ = gJ;
     w.dJdT_in = dJdT;
     w.grad_T = grad_T;  // pass E writes gJ dJ/dT
     cd* gout = w.G;  // band result in the work space, converted below (rfft layout)
     if (layout == LOOP_LAYOUT_BAND) w.G = reinterpret_cast<cd*>(grad_u);
-    if ((st = launch_AC(s, w, tw, hs))) return st;
+    if (usave) w.A = const_cast<cd*>(reinterpret_cast<const cd*>(usave));  // u on the s grid, from the forward
+    if ((st = launch_AC(s, w, tw, hs, usave == nullptr))) return st;
     if ((st = launch_D(s, w, const_cast<double*>(T), MODE_ADJOINT, 0.0, nullptr, nullptr, nullptr, tw, hs))) return st;
     if ((st = launch_E(s, w, MODE_ADJOINT, 0.0, 0, 0, tw, hs, T))) return st;
     if (layout == LOOP_LAYOUT_RFFT) launch_from_band(s, gout, reinterpret_cast<cd*>(grad_u), hs);

@@ -220,7 +220,9 @@ __device__ __forceinline__ void col_pass_A(const Shape& sh, int block, const Wor
 
 // Reverse mode, first pass: the inverse s-transforms of u_hat (into A, as pass A) and of
 // i q r_hat from the saved residual (into C, as pass C would leave it), column by column.
-template <int N>
+// Without WITH_U, A holds u on the s grid already (saved by the forward) and only the
+// residual is transformed.
+template <int N, bool WITH_U = true>
 __device__ __forceinline__ void col_pass_AC(const Shape& sh, int block, const Work& w, cd* ex,
                                             const cd* __restrict__ tw) {
     using G = ColG<N>;
@@ -228,13 +230,14 @@ __device__ __forceinline__ void col_pass_AC(const Shape& sh, int block, const Wo
     TwCache<N, G::PT> twc;
     tw_cache_load<N, G::PT>(twc, p.t, tw);
     const size_t col = (size_t)p.l * sh.C + p.j;
-    const cd* u = w.U + col * sh.NB;
     const cd* r = w.R + col * sh.NB;
     const double q = kTwoPi * p.j / sh.L;
     cd v[G::PT], rv[G::PT];
-    band_prefetch<N>(sh, p, u, w.herm0, v);
-    band_prefetch<N>(sh, p, r, 0, rv);  // in flight during the first transform
-    col_inverse_store<N>(sh, p, v, w.A, ex, twc);
+    band_prefetch<N>(sh, p, r, 0, rv);  // with WITH_U, in flight during the first transform
+    if constexpr (WITH_U) {
+        band_prefetch<N>(sh, p, w.U + col * sh.NB, w.herm0, v);
+        col_inverse_store<N>(sh, p, v, w.A, ex, twc);
+    }
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) v[m] = cd{-q * rv[m].y, q * rv[m].x};  // i q r (zero outside the band)
     col_inverse_store<N>(sh, p, v, w.Cb, ex, twc);

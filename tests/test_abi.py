@@ -99,16 +99,23 @@ def test_reverse_mode_entry_points_reject_bad_arguments_on_host():
     ws = ctypes.c_void_p(1 << 24)
     E, W = _lib.LOOP_EINVAL, _lib.LOOP_EWORKSPACE
     band, rfft = _lib.LAYOUT_BAND, _lib.LAYOUT_RFFT
+    fake4 = ctypes.c_void_p(1 << 23)
     fwd = L.loop_cost_fwd
-    assert fwd(22.0, 32, 32, 1, 7, fake, fake, fake2, None, fake3, ws, 1 << 30, None) == E  # layout
-    assert fwd(22.0, 32, 32, 1, rfft, fake, odd, fake2, None, fake3, ws, 1 << 30, None) == E  # misaligned u
-    assert fwd(22.0, 32, 32, 1, band, fake, fake3, fake2, None, fake3, ws, 1 << 30, None) == E  # rsave aliases u
-    assert fwd(22.0, 32, 32, 1, band, fake, fake, fake2, None, fake3, ws, 1024, None) == W
+    assert fwd(22.0, 32, 32, 1, 7, fake, fake, fake2, None, fake3, None, ws, 1 << 30, None) == E  # layout
+    assert fwd(22.0, 32, 32, 1, rfft, fake, odd, fake2, None, fake3, None, ws, 1 << 30, None) == E  # misaligned u
+    assert fwd(22.0, 32, 32, 1, band, fake, fake3, fake2, None, fake3, None, ws, 1 << 30, None) == E  # rsave = u
+    assert fwd(22.0, 32, 32, 1, band, fake, fake, fake2, None, fake3, fake3, ws, 1 << 30, None) == E  # usave = rsave
+    assert fwd(22.0, 32, 32, 1, band, fake, fake, fake2, None, fake3, fake, ws, 1 << 30, None) == E  # usave = u
+    assert fwd(22.0, 32, 32, 1, band, fake, fake, fake2, None, fake3, odd, ws, 1 << 30, None) == E  # misaligned
+    assert fwd(22.0, 32, 32, 1, band, fake, fake, fake2, None, fake3, None, ws, 1024, None) == W
+    assert fwd(22.0, 32, 32, 1, band, fake, fake, fake2, None, fake3, fake4, ws, 1024, None) == W
     bwd = L.loop_cost_bwd
-    assert bwd(22.0, 32, 32, 1, rfft, fake, fake, fake2, fake, None, fake, None, ws, 1 << 30, None) == E  # grad = u
-    assert bwd(22.0, 32, 32, 1, rfft, fake, fake, fake2, fake, None, fake2, None, ws, 1 << 30, None) == E  # = rsave
+    assert bwd(22.0, 32, 32, 1, rfft, fake, fake, fake2, None, fake, None, fake, None, ws, 1 << 30, None) == E  # grad = u
+    assert bwd(22.0, 32, 32, 1, rfft, fake, fake, fake2, None, fake, None, fake2, None, ws, 1 << 30, None) == E  # = rsave
+    assert bwd(22.0, 32, 32, 1, rfft, fake, fake, fake2, fake4, fake, None, fake4, None, ws, 1 << 30, None) == E  # = usave
+    assert bwd(22.0, 32, 32, 1, rfft, fake, fake, fake2, odd, fake, None, fake3, None, ws, 1 << 30, None) == E  # usave
     bad8 = ctypes.c_void_p((1 << 20) + 4)
-    assert bwd(22.0, 32, 32, 1, band, fake, fake, fake2, bad8, None, fake3, fake, ws, 1 << 30, None) == E  # dJdT
+    assert bwd(22.0, 32, 32, 1, band, fake, fake, fake2, None, bad8, None, fake3, fake, ws, 1 << 30, None) == E  # dJdT
     upd = L.loop_update_grad
     assert upd(22.0, 32, 32, 1, band, fake, fake2, fake2, fake, 1e-4, 1, None) == E  # grad aliases u
     assert upd(22.0, 32, 32, 1, band, fake, fake2, fake3, fake, 0.0, 1, None) == E  # dtau

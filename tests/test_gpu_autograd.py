@@ -4,10 +4,10 @@ backward is the hand-written adjoint kernel (loop_cost_fwd / loop_cost_bwd).
 Checks: forward against the oracle's J; backward against the oracle's gradient (which
 test_oracle.py pins against torch's own autograd through torch.fft); central finite
 differences of the GPU forward in 32 random unit directions of (u_hat, T) at h = 1e-6 (the
-64 x 256, L = 39 differentiation workload); torch.autograd.gradcheck on a small grid; that the
-Function saves its inputs and the band residual only (the transform intermediates are
-recomputed, not stored); the band-layout form against the rfft-layout one; and the step from
-the gradient (loop_update_grad) against the fused step.
+64 x 256, L = 39 differentiation workload); torch.autograd.gradcheck on a small grid; what the
+Function saves (the inputs, the band residual and, by default, u on the s grid); that the
+reverse pass from the saved u equals the one that recomputes it; the band-layout form against
+the rfft-layout one; and the step from the gradient (loop_update_grad) against the fused step.
 """
 import numpy as np
 import pytest
@@ -97,18 +97,69 @@ def test_gradcheck_small_grid(ag):
                                     rtol=1e-5)
 
 
-def test_backward_recomputes_instead_of_storing(ag):
-    """The context holds the inputs, the band residual (C x NB per loop, smaller than the input)
-    and dJ/dT: no grid-sized transform intermediate (C x Ns or more per loop)."""
+def test_saved_tensors(ag):
+    """With save_u false the context holds the inputs, the band residual (C x NB per loop,
+    smaller than the input) and dJ/dT: no grid-sized transform intermediate (C x Ns or more per
+    loop). With save_u (the default) it holds u on the s grid besides, C x Ns per loop; without
+    a gradient to take it holds nothing grid-sized either."""
     spec = loopgen.config_loops(3)[0]
     u = torch.from_numpy(spec.uhat[None]).to(DEV).requires_grad_(True)
     T = torch.tensor([spec.T], dtype=torch.float64, device=DEV, requires_grad=True)
-    J = ag.LoopCost.apply(u, T, spec.L)
-    saved = J.grad_fn.saved_tensors
     C, NB = (spec.Nx - 1) // 3 + 1, 2 * ((spec.Ns - 1) // 3) + 1
+    J = ag.LoopCost.apply(u, T, spec.L, False)
+    saved = J.grad_fn.saved_tensors
     assert len(saved) == 4 and saved[0].shape == u.shape and saved[1].shape == T.shape
     assert tuple(saved[2].shape) == (1, C, NB) and tuple(saved[3].shape) == (1,)
     assert all(t.numel() < C * spec.Ns for t in saved[1:])
+    J = ag.LoopCost.apply(u, T, spec.L)
+    saved = J.grad_fn.saved_tensors
+    assert len(saved) == 5 and tuple(saved[4].shape) == (1, C, spec.Ns)
+    J = ag.LoopCost.apply(u.detach(), T.detach().requires_grad_(True), spec.L)
+    assert len(J.grad_fn.saved_tensors) == 5
+    with torch.no_grad():
+        J = ag.LoopCost.apply(u, T, spec.L)
+    assert J.grad_fn is None
+
+
+@pytest.mark.parametrize("layout", ["rfft", "band"])
+def test_saved_u_gives_the_recomputed_gradient_bitwise(ag, layout):
+    """The reverse pass from the forward's u on the s grid equals the one that recomputes it, bit
+    for bit (the same column transform, run once instead of twice), through the C-ABI and through
+    the autograd Functions; the saved u is the forward's inverse s-transform of each column."""
+    from paper_2007_06427_amd import api
+    specs = loopgen.config_loops(5, 2) + [loopgen.random_loop(78, 100.0, 256, 1024, 40, 100, 0.5, 0.05, 40.0)]
+    L, Nx, Ns = 100.0, 256, 1024
+    u = torch.from_numpy(np.stack([s.uhat for s in specs])).to(DEV)
+    T = torch.tensor([s.T for s in specs], dtype=torch.float64, device=DEV)
+    kw = {"layout": api.LAYOUT_BAND, "grid": (Nx, Ns)} if layout == "band" else {}
+    x = api.to_band(u) if layout == "band" else u
+    us = api.saved_u(len(specs), Nx, Ns, DEV)
+    J, dJdT, rs = api.loop_cost_fwd(x, T, L, **kw)
+    J2, dJdT2, rs2 = api.loop_cost_fwd(x, T, L, usave=us, **kw)
+    assert torch.equal(J, J2) and torch.equal(dJdT, dJdT2) and torch.equal(rs, rs2)
+    gJ = torch.tensor([0.5, -2.0, 1.0], dtype=torch.float64, device=DEV)
+    gu, gT = api.loop_cost_bwd(x, T, L, rs, dJdT, gJ, **kw)
+    gu2, gT2 = api.loop_cost_bwd(x, T, L, rs, dJdT, gJ, usave=us, **kw)
+    assert torch.equal(gu, gu2) and torch.equal(gT, gT2)
+    # the saved u: column j of loop l, inverse s-transform (numpy) of the band coefficients
+    C = (Nx - 1) // 3 + 1
+    uc = np.stack([K.canonical(s.uhat) for s in specs])[:, :, :C]  # (l, Ns, C)
+    want = np.fft.ifft(uc, axis=1) * Ns  # u_j(s_n) = sum_k u_hat_{j,k} e^{2 pi i k n / Ns}
+    got = us.cpu().numpy().transpose(0, 2, 1)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    # the Functions with and without it
+    grads = []
+    for save in (False, True):
+        xa = x.clone().requires_grad_(True)
+        Ta = T.clone().requires_grad_(True)
+        if layout == "band":
+            Jf = ag.LoopCostBand.apply(xa, Ta, L, Nx, Ns, save)
+        else:
+            Jf = ag.LoopCost.apply(xa, Ta, L, save)
+        (Jf * gJ).sum().backward()
+        grads.append((xa.grad, Ta.grad))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+    assert torch.equal(grads[0][0], gu)
 
 
 def test_reverse_pass_equals_adjoint_grad_bitwise(ag):
