@@ -422,26 +422,26 @@ def autograd_kernel_bytes(Nx, Ns):
       forward  k_colA  reads u_hat, writes A                 S + W
                k_rowB  reads A, writes B                     2W
                k_colC  reads B and u_hat, writes r_hat       W + 2S
-      backward k_colR  reads r_hat, writes C                 S + W
-               k_rowD  reads A (kept from the forward) and C, writes D   3W
+      backward k_colAC reads u_hat and r_hat, writes A, C    2S + 2W
+               k_rowD  reads A and C, writes D               3W
                k_colE  reads D and r_hat, writes the grad    W + 2S
       update   k_update_grad_band reads u_hat, grad; writes u_hat   3S
-    16 (9W + 9S) per loop-step; the per-loop scalars (J, dJ/dT, T) are left out. (Without the
-    kept A, the backward's first kernel k_colAC also reads u_hat and writes A: 16 (10W + 10S).)"""
+    16 (10W + 10S) per loop-step; the per-loop scalars (J, dJ/dT, T) are left out. (With u on the
+    s grid kept from the forward, k_colR reads r_hat and writes C alone: 16 (9W + 9S).)"""
     W, S = band(Nx, Ns)
     return {f"k_colA<{Ns}>": 16 * (S + W), f"k_rowB<{Nx}>": 16 * 2 * W, f"k_colC<{Ns}, 0>": 16 * (W + 2 * S),
-            f"k_colR<{Ns}>": 16 * (S + W), f"k_rowD<{Nx}>": 16 * 3 * W, f"k_colE<{Ns}, 4>": 16 * (W + 2 * S),
+            f"k_colAC<{Ns}>": 16 * (2 * S + 2 * W), f"k_rowD<{Nx}>": 16 * 3 * W, f"k_colE<{Ns}, 4>": 16 * (W + 2 * S),
             "k_update_grad_band": 16 * 3 * S}
 
 
 def bench_autograd(args, cfg, specs, steps, dtau, scheme):
-    """The large batched workload as specified: per step, J = LoopCostBand(u_hat, T) forward
-    (keeping u on the s grid for the backward), J.backward() through the hand-written adjoint
-    kernels, and one fused update kernel
+    """The large batched workload as specified: per step, J = LoopCostBand(u_hat, T) forward,
+    J.backward() through the hand-written adjoint kernels (which recompute the transform
+    intermediates instead of storing them), and one fused update kernel
     (loop_update_grad) that takes the gradient: G_1 = -grad / (w_j L), the IMEX step of u_hat and
     the explicit step of T. The state is held in the band layout (the retained modes); the
     conversion from and to the rfft layout is inside the timed region, once. Beside it: the same
-    path on rfft-layout tensors (LoopCost), the band path whose backward recomputes u instead,
+    path on rfft-layout tensors (LoopCost), the band path that keeps u on the s grid (save_u),
     the fused batched step (loop_batch_step, tuned) and the plain method (loop_step per loop), all
     on the same loops, and the CPU oracle."""
     import numpy as np
@@ -460,7 +460,7 @@ def bench_autograd(args, cfg, specs, steps, dtau, scheme):
     ones = torch.ones(nl, dtype=torch.float64, device=dev)
     ws = api.workspace(Nx, Ns, nl)
 
-    def run_band(ub, T, k, save_u=True):
+    def run_band(ub, T, k, save_u=False):
         for _ in range(k):
             ua = ub.detach().requires_grad_(True)
             Ta = T.detach().requires_grad_(True)
@@ -522,7 +522,7 @@ def bench_autograd(args, cfg, specs, steps, dtau, scheme):
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, dom),
                 "kernel": dom, "bytes_per_launch": by, "avg_launch_us": round(kern[dom]["avg_us"], 2),
-                "byte_model": "16 (9W + 9S) B per loop-step over seven kernels (W = C Ns, S = C NB)",
+                "byte_model": "16 (10W + 10S) B per loop-step over seven kernels (W = C Ns, S = C NB)",
                 "kernels_us": {k: round(v["avg_us"], 2) for k, v in tr.kernels.items()},
                 "kernels_frac": {k: round(kb[k] * nl / (v["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
                                  for k, v in kern.items()},
@@ -536,13 +536,14 @@ def bench_autograd(args, cfg, specs, steps, dtau, scheme):
     rfft_path(min(args.warmup, 5))
     wall_r, gpu_r, (u_r, T_r) = timed(rfft_path, k_r)
 
-    # ---- the band path with the backward recomputing u on the s grid (nothing grid-sized kept)
-    def band_recompute(k):
+    # ---- the band path with u on the s grid kept from the forward (save_u): one column
+    # transform fewer in the backward, a grid-sized saved tensor
+    def band_saved(k):
         ub, T = api.to_band(u0), T0.clone()
-        run_band(ub, T, k, save_u=False)
+        run_band(ub, T, k, save_u=True)
         return api.from_band(ub, Nx, Ns), T
-    band_recompute(min(args.warmup, 5))
-    wall_n, gpu_n, (u_n, _) = timed(band_recompute, k_r)
+    band_saved(min(args.warmup, 5))
+    wall_n, gpu_n, (u_n, _) = timed(band_saved, k_r)
     if k_r == steps:  # the same steps: the same state, bit for bit
         assert torch.equal(u_n, u_ag)
 
@@ -597,10 +598,10 @@ def bench_autograd(args, cfg, specs, steps, dtau, scheme):
         "autograd_rfft_layout": {"value": pts_step * k_r / wall_r, "unit": "pts/s", "steps": k_r,
                                  "gpu_ms_per_step": gpu_r / k_r * 1e3,
                                  "method": "LoopCost on rfft-layout tensors + loop_update_grad"},
-        "autograd_recompute_u": {"value": pts_step * k_r / wall_n, "unit": "pts/s", "steps": k_r,
-                                 "gpu_ms_per_step": gpu_n / k_r * 1e3,
-                                 "method": "LoopCostBand with save_u false: the backward recomputes u on the "
-                                           "s grid (k_colAC in place of k_colR), state-sized saved tensors only"},
+        "autograd_saved_u": {"value": pts_step * k_r / wall_n, "unit": "pts/s", "steps": k_r,
+                             "gpu_ms_per_step": gpu_n / k_r * 1e3,
+                             "method": "LoopCostBand with save_u: u on the s grid kept from the forward "
+                                       "(k_colR in place of k_colAC), a grid-sized saved tensor"},
         "fused": {"value": pts_step * steps / wall_f, "unit": "pts/s", "steps": steps,
                   "gpu_ms_per_step": gpu_f / steps * 1e3, "schedule": tuning["schedule"],
                   "variants": tuning["variants"], "method": "loop_batch_step (all steps in one call)"},

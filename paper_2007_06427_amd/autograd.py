@@ -7,11 +7,11 @@
 The forward is loop_cost_fwd: J, dJ/dT and the band residual r_hat, which the context keeps.
 The backward is loop_cost_bwd: it applies the adjoint operator to the saved residual and
 returns the gradient in torch's complex convention, d/dRe + i d/dIm, which is -w_j L G_1 in
-the band, and dJ/dT for the periods (Sec. 3, eq. KS_G with J halved). u on the s grid, which
-the backward needs, is kept from the forward when save_u is true (the default: nloops x C x Ns
-complex values, 1.5 times the band state at 256 x 1024, and one column transform fewer in the
-backward); with save_u false the backward recomputes it and the context holds only
-state-sized tensors. Both give the same gradient bit for bit.
+the band, and dJ/dT for the periods (Sec. 3, eq. KS_G with J halved). By default the backward
+recomputes u on the s grid from u_hat, so the context holds only state-sized tensors and no
+transform intermediate. save_u=True keeps that intermediate from the forward instead
+(nloops x C x Ns complex values, 1.5 times the band state at 256 x 1024) and saves the
+backward one column transform. Both give the same gradient bit for bit.
 """
 from __future__ import annotations
 
@@ -28,7 +28,7 @@ def _usave(ctx, nl, Nx, Ns, device, save_u):
 
 class LoopCost(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, uhat, T, L, save_u=True):
+    def forward(ctx, uhat, T, L, save_u=False):
         uhat = uhat.contiguous()
         T = T.contiguous()
         ctx.L = float(L)
@@ -49,7 +49,7 @@ class LoopCost(torch.autograd.Function):
 
 class LoopCostBand(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, ub, T, L, Nx, Ns, save_u=True):
+    def forward(ctx, ub, T, L, Nx, Ns, save_u=False):
         ub = ub.contiguous()
         T = T.contiguous()
         ctx.L, ctx.grid = float(L), (int(Nx), int(Ns))
@@ -67,11 +67,11 @@ class LoopCostBand(torch.autograd.Function):
         return gu, gT, None, None, None, None
 
 
-def loop_cost(uhat, T, L, save_u=True):
+def loop_cost(uhat, T, L, save_u=False):
     """Differentiable J = 1/2 int int r^2 per loop (rfft layout)."""
     return LoopCost.apply(uhat, T, L, save_u)
 
 
-def loop_cost_band(ub, T, L, Nx, Ns, save_u=True):
+def loop_cost_band(ub, T, L, Nx, Ns, save_u=False):
     """Differentiable J = 1/2 int int r^2 per loop (band layout)."""
     return LoopCostBand.apply(ub, T, L, Nx, Ns, save_u)

@@ -74,8 +74,8 @@ def test_flop_model_counts_every_transform():
 
 
 def test_autograd_kernels_add_up_to_their_step_model():
-    """The seven kernels of an autograd-path step move 16 (9W + 9S) bytes per loop."""
+    """The seven kernels of an autograd-path step move 16 (10W + 10S) bytes per loop."""
     for Nx, Ns in [(64, 256), (256, 1024)]:
         W, S = bench.band(Nx, Ns)
         kb = bench.autograd_kernel_bytes(Nx, Ns)
-        assert len(kb) == 7 and sum(kb.values()) == 16 * (9 * W + 9 * S)
+        assert len(kb) == 7 and sum(kb.values()) == 16 * (10 * W + 10 * S)

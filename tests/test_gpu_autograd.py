@@ -5,8 +5,8 @@ Checks: forward against the oracle's J; backward against the oracle's gradient (
 test_oracle.py pins against torch's own autograd through torch.fft); central finite
 differences of the GPU forward in 32 random unit directions of (u_hat, T) at h = 1e-6 (the
 64 x 256, L = 39 differentiation workload); torch.autograd.gradcheck on a small grid; what the
-Function saves (the inputs, the band residual and, by default, u on the s grid); that the
-reverse pass from the saved u equals the one that recomputes it; the band-layout form against
+Function saves (the inputs and the band residual; u on the s grid only when asked); that the
+reverse pass from a saved u equals the one that recomputes it; the band-layout form against
 the rfft-layout one; and the step from the gradient (loop_update_grad) against the fused step.
 """
 import numpy as np
@@ -98,26 +98,25 @@ def test_gradcheck_small_grid(ag):
 
 
 def test_saved_tensors(ag):
-    """With save_u false the context holds the inputs, the band residual (C x NB per loop,
-    smaller than the input) and dJ/dT: no grid-sized transform intermediate (C x Ns or more per
-    loop). With save_u (the default) it holds u on the s grid besides, C x Ns per loop; without
-    a gradient to take it holds nothing grid-sized either."""
+    """By default the context holds the inputs, the band residual (C x NB per loop, smaller than
+    the input) and dJ/dT: no grid-sized transform intermediate (C x Ns or more per loop), the
+    backward recomputes them. With save_u it holds u on the s grid besides, C x Ns per loop."""
     spec = loopgen.config_loops(3)[0]
     u = torch.from_numpy(spec.uhat[None]).to(DEV).requires_grad_(True)
     T = torch.tensor([spec.T], dtype=torch.float64, device=DEV, requires_grad=True)
     C, NB = (spec.Nx - 1) // 3 + 1, 2 * ((spec.Ns - 1) // 3) + 1
-    J = ag.LoopCost.apply(u, T, spec.L, False)
-    saved = J.grad_fn.saved_tensors
-    assert len(saved) == 4 and saved[0].shape == u.shape and saved[1].shape == T.shape
-    assert tuple(saved[2].shape) == (1, C, NB) and tuple(saved[3].shape) == (1,)
-    assert all(t.numel() < C * spec.Ns for t in saved[1:])
-    J = ag.LoopCost.apply(u, T, spec.L)
+    for J in (ag.LoopCost.apply(u, T, spec.L), ag.loop_cost(u, T, spec.L)):
+        saved = J.grad_fn.saved_tensors
+        assert len(saved) == 4 and saved[0].shape == u.shape and saved[1].shape == T.shape
+        assert tuple(saved[2].shape) == (1, C, NB) and tuple(saved[3].shape) == (1,)
+        assert all(t.numel() < C * spec.Ns for t in saved[1:])
+    J = ag.LoopCost.apply(u, T, spec.L, True)
     saved = J.grad_fn.saved_tensors
     assert len(saved) == 5 and tuple(saved[4].shape) == (1, C, spec.Ns)
-    J = ag.LoopCost.apply(u.detach(), T.detach().requires_grad_(True), spec.L)
+    J = ag.LoopCost.apply(u.detach(), T.detach().requires_grad_(True), spec.L, True)
     assert len(J.grad_fn.saved_tensors) == 5
     with torch.no_grad():
-        J = ag.LoopCost.apply(u, T, spec.L)
+        J = ag.LoopCost.apply(u, T, spec.L, True)
     assert J.grad_fn is None
 
 
