@@ -367,9 +367,10 @@ int loop_batch_autotune(void* plan, const double* T, const double* uhat_pool, in
                         size_t ws_bytes, void* stream);
 
 /* Kernel timing. Between loop_trace_start and loop_trace_stop, every pass kernel the library
- * queues (and the conversions, finalize and update kernels) is bracketed by two HIP events
- * recorded on the stream it is launched on. loop_trace_stop ends recording, waits for the
- * recorded events and sums the durations per kernel; loop_trace_count and loop_trace_get
+ * queues (and the conversions, finalize and update kernels) is launched with two HIP events
+ * that its own dispatch records at the kernel's start and end (hipExtLaunchKernelGGL), so a
+ * duration is the kernel's alone, as a profiler's kernel trace measures it. loop_trace_stop
+ * ends recording, waits for the recorded events and sums the durations per kernel; loop_trace_count and loop_trace_get
  * then report, per kernel name (as in "k_rowD<256>" or "k_rag<3, 1>", in order of first
  * launch): launches, total, shortest and longest duration in microseconds. Host calls that
  * create events: not for use under stream capture. loop_trace_stop returns LOOP_EHIP if an

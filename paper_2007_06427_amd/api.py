@@ -524,7 +524,8 @@ class Batch:
 
 
 class trace:
-    """Kernel timing by HIP events around each library launch (see loop_trace_start):
+    """Kernel timing by HIP events that each library launch's dispatch records at its kernel's
+    start and end (see loop_trace_start):
 
         with api.trace() as tr:
             ...                       # library calls

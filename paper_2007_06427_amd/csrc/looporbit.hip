@@ -2,6 +2,7 @@
 // (Azimi, Ashtari & Schneider, arXiv:2007.06427, Sec. 3-4). See include/looporbit.h for the
 // contract of each entry point and passes.hpp for the pass decomposition.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdint>
@@ -715,15 +716,17 @@ __global__ __launch_bounds__(kBlock) void k_rag(BatchArgs a, const uint32_t* __r
     }
 }
 
-template <int PASS>
-void launch_rag(int v, dim3 grid, size_t lds, hipStream_t hs, const BatchArgs& a, const uint32_t* c, int step) {
+// ts: the launch's TraceScope
+template <int PASS, class Scope>
+void launch_rag(int v, dim3 grid, size_t lds, hipStream_t hs, const BatchArgs& a, const uint32_t* c, int step,
+                Scope& ts) {
+    const uint32_t sh = (uint32_t)lds;
     switch (v) {
-        case 0: hipLaunchKernelGGL((k_rag<PASS, 0>), grid, dim3(kBlock), lds, hs, a, c, step); break;
-        case 1: hipLaunchKernelGGL((k_rag<PASS, 1>), grid, dim3(kBlock), lds, hs, a, c, step); break;
-        case 2: hipLaunchKernelGGL((k_rag<PASS, 2>), grid, dim3(kBlock), lds, hs, a, c, step); break;
+        case 0: ts.launch(k_rag<PASS, 0>, grid, dim3(kBlock), sh, hs, a, c, step); break;
+        case 1: ts.launch(k_rag<PASS, 1>, grid, dim3(kBlock), sh, hs, a, c, step); break;
+        case 2: ts.launch(k_rag<PASS, 2>, grid, dim3(kBlock), sh, hs, a, c, step); break;
         default:
-            if constexpr (is_row_pass(PASS))
-                hipLaunchKernelGGL((k_rag<PASS, 3>), grid, dim3(kBlock), lds, hs, a, c, step);
+            if constexpr (is_row_pass(PASS)) ts.launch(k_rag<PASS, 3>, grid, dim3(kBlock), sh, hs, a, c, step);
             break;
     }
 }
@@ -1036,9 +1039,9 @@ int prepare(double L, int Nx, int Ns, int nloops, void* ws, size_t ws_bytes, Sha
 }
 
 // ---------------------------------------------------------------------------- kernel timing
-// While tracing is on (loop_trace_start), each traced launch is bracketed by two HIP events
-// recorded on the launch's own stream; loop_trace_stop reads them and sums the durations per
-// kernel. Off (the default), a TraceScope costs one relaxed atomic load.
+// While tracing is on (loop_trace_start), each traced launch records two HIP events at its
+// kernel's start and end; loop_trace_stop reads them and sums the durations per kernel. Off
+// (the default), a TraceScope costs one relaxed atomic load.
 std::atomic<int> g_trace_on{0};
 struct TraceRec {
     std::string name;
@@ -1066,29 +1069,42 @@ hipEvent_t trace_event() {
 }
 
 struct TraceScope {
-    hipEvent_t a = nullptr;
-    hipStream_t st = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool launched = false;
     std::string name;
     TraceScope(const char* base, int size, hipStream_t s) : TraceScope(base, size, -1, s) {}
-    TraceScope(const char* base, int size, int size2, hipStream_t s) {
+    TraceScope(const char* base, int size, int size2, hipStream_t) {
         if (!g_trace_on.load(std::memory_order_relaxed)) return;
         std::lock_guard<std::mutex> g(g_trace_mu);
         a = trace_event();
-        if (!a || hipEventRecord(a, s) != hipSuccess) {
+        b = a ? trace_event() : nullptr;
+        if (!a || !b) {
             g_trace_failed = true;
-            a = nullptr;
+            if (a) g_trace_pool.push_back(a);
+            a = b = nullptr;
             return;
         }
-        st = s;
         name = std::string(base);
         if (size > 0) name += "<" + std::to_string(size) + (size2 >= 0 ? ", " + std::to_string(size2) : "") + ">";
+    }
+    // The scope's one launch. While tracing, the dispatch records the start and stop events
+    // itself (hipExtLaunchKernelGGL), so the duration is the kernel's own, as a profiler's
+    // kernel trace reports it.
+    template <class K, class... Args>
+    void launch(K kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, Args... args) {
+        if (a) {
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, a, b, 0, args...);
+            launched = true;
+        } else {
+            hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+        }
     }
     ~TraceScope() {
         if (!a) return;
         std::lock_guard<std::mutex> g(g_trace_mu);
-        hipEvent_t b = trace_event();
-        if (!b || hipEventRecord(b, st) != hipSuccess) {
-            g_trace_failed = true;
+        if (!launched) {  // nothing was launched: return the events unused
+            g_trace_pool.push_back(a);
+            g_trace_pool.push_back(b);
             return;
         }
         g_trace_recs.push_back(TraceRec{name, a, b});
@@ -1131,12 +1147,12 @@ unsigned row_blocks(const Shape& s) {
 
 int launch_A(const Shape& s, const Work& w, const cd* tw, hipStream_t st) {
     LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colA", S_, st);
-                   hipLaunchKernelGGL(k_colA<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
+                   ts_.launch(k_colA<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
     return LOOP_OK;
 }
 int launch_B(const Shape& s, const Work& w, const cd* tw, hipStream_t st) {
     LO_SWITCH_SIZE(s.M, TraceScope ts_("k_rowB", S_, st);
-                   hipLaunchKernelGGL(k_rowB<S_>, dim3(row_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
+                   ts_.launch(k_rowB<S_>, dim3(row_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
     return LOOP_OK;
 }
 int launch_C(const Shape& s, const double* T, const Work& w, int mode, double dtau, int scheme, const cd* tw,
@@ -1144,7 +1160,7 @@ int launch_C(const Shape& s, const double* T, const Work& w, int mode, double dt
     auto launch = [&](auto md) {
         constexpr int MD = decltype(md)::value;
         LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colC", S_, MD, st);
-                       hipLaunchKernelGGL((k_colC<S_, MD>), dim3(col_blocks(s)), dim3(kBlock), 0, st, s, T, w, dtau,
+                       ts_.launch((k_colC<S_, MD>), dim3(col_blocks(s)), dim3(kBlock), 0, st, s, T, w, dtau,
                                           scheme, tw));
         return LOOP_OK;
     };
@@ -1159,7 +1175,7 @@ int launch_C(const Shape& s, const double* T, const Work& w, int mode, double dt
 int launch_D(const Shape& s, const Work& w, double* T, int mode, double dtau, double* J_hist, double* Jout,
              double* dJdTout, const cd* tw, hipStream_t st) {
     LO_SWITCH_SIZE(s.M, TraceScope ts_("k_rowD", S_, st);
-                   hipLaunchKernelGGL(k_rowD<S_>, dim3(row_blocks(s)), dim3(kBlock), 0, st, s, w, T, mode,
+                   ts_.launch(k_rowD<S_>, dim3(row_blocks(s)), dim3(kBlock), 0, st, s, w, T, mode,
                                            dtau, J_hist, Jout, dJdTout, tw));
     return LOOP_OK;
 }
@@ -1168,7 +1184,7 @@ int launch_E(const Shape& s, const Work& w, int mode, double dtau, int scheme, i
     auto launch = [&](auto md) {
         constexpr int MD = decltype(md)::value;
         LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colE", S_, MD, st);
-                       hipLaunchKernelGGL((k_colE<S_, MD>), dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, dtau,
+                       ts_.launch((k_colE<S_, MD>), dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, dtau,
                                           scheme, fuseA, tw, T));
         return LOOP_OK;
     };
@@ -1182,22 +1198,22 @@ int launch_E(const Shape& s, const Work& w, int mode, double dtau, int scheme, i
 int launch_AC(const Shape& s, const Work& w, const cd* tw, hipStream_t st, bool with_u) {
     if (!with_u) {
         LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colR", S_, st);
-                       hipLaunchKernelGGL(k_colR<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
+                       ts_.launch(k_colR<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
         return LOOP_OK;
     }
     LO_SWITCH_SIZE(s.N, TraceScope ts_("k_colAC", S_, st);
-                   hipLaunchKernelGGL(k_colAC<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
+                   ts_.launch(k_colAC<S_>, dim3(col_blocks(s)), dim3(kBlock), 0, st, s, w, tw));
     return LOOP_OK;
 }
 void launch_to_band(const Shape& s, const cd* uhat, cd* U, hipStream_t st) {
     dim3 grid((s.NB + 31) / 32, (s.C + 31) / 32, s.nloops);
     TraceScope ts_("k_to_band", 0, st);
-    hipLaunchKernelGGL(k_to_band, grid, dim3(256), 0, st, s, uhat, U);
+    ts_.launch(k_to_band, grid, dim3(256), 0, st, s, uhat, U);
 }
 void launch_from_band(const Shape& s, const cd* src, cd* out, hipStream_t st) {
     dim3 grid((s.N + 31) / 32, (s.H + 31) / 32, s.nloops);
     TraceScope ts_("k_from_band", 0, st);
-    hipLaunchKernelGGL(k_from_band, grid, dim3(256), 0, st, s, src, out);
+    ts_.launch(k_from_band, grid, dim3(256), 0, st, s, src, out);
 }
 
 // Raise kernel k's dynamic-LDS limit to `bytes` on the current device, once: the setting is
@@ -1377,7 +1393,7 @@ int launch_resident(const Shape& s, cd* u, double* T, double dtau, int scheme, i
                 auto k = k_resident<M_, N_>;
                 if ((st = ensure_lds_limit(reinterpret_cast<const void*>(k), R::BYTES))) return;
                 TraceScope ts_("k_resident", M_, N_, hs);
-                hipLaunchKernelGGL(k, dim3(s.nloops), dim3(kBlock), R::BYTES, hs, s, u, u, T, dtau, scheme, nsteps,
+                ts_.launch(k, dim3(s.nloops), dim3(kBlock), R::BYTES, hs, s, u, u, T, dtau, scheme, nsteps,
                                    J_hist, status, tw);
                 st = last_error();
             }
@@ -1717,7 +1733,7 @@ int loop_cost_fwd(double L, int Nx, int Ns, int nloops, int layout, const double
     if ((st = launch_C(s, T, w, MODE_RESIDUAL, 0.0, 0, tw, hs))) return st;
     {
         TraceScope ts_("k_finalize", 0, hs);
-        hipLaunchKernelGGL(k_finalize, dim3(nloops), dim3(64), 0, hs, s, w, const_cast<double*>(T), J, dJdT);
+        ts_.launch(k_finalize, dim3(nloops), dim3(64), 0, hs, s, w, const_cast<double*>(T), J, dJdT);
     }
     return last_error();
 }
@@ -1766,16 +1782,16 @@ int loop_update_grad(double L, int Nx, int Ns, int nloops, int layout, double* T
     hipStream_t hs = (hipStream_t)stream;
     if (layout == LOOP_LAYOUT_RFFT) {
         TraceScope ts_("k_update_grad", 0, hs);
-        hipLaunchKernelGGL(k_update_grad, dim3(elem_blocks((size_t)s.nloops * s.N * s.H)), dim3(256), 0, hs, s, T,
+        ts_.launch(k_update_grad, dim3(elem_blocks((size_t)s.nloops * s.N * s.H)), dim3(256), 0, hs, s, T,
                            reinterpret_cast<cd*>(u), reinterpret_cast<const cd*>(grad_u), dtau, scheme);
     } else {
         TraceScope ts_("k_update_grad_band", 0, hs);
-        hipLaunchKernelGGL(k_update_grad_band, dim3(elem_blocks((size_t)s.nloops * s.C * s.NB)), dim3(256), 0, hs, s,
+        ts_.launch(k_update_grad_band, dim3(elem_blocks((size_t)s.nloops * s.C * s.NB)), dim3(256), 0, hs, s,
                            T, reinterpret_cast<cd*>(u), reinterpret_cast<const cd*>(grad_u), dtau, scheme);
     }
     {
         TraceScope ts_("k_update_T", 0, hs);
-        hipLaunchKernelGGL(k_update_T, dim3((nloops + 255) / 256), dim3(256), 0, hs, nloops, T, grad_T, dtau);
+        ts_.launch(k_update_T, dim3((nloops + 255) / 256), dim3(256), 0, hs, nloops, T, grad_T, dtau);
     }
     return last_error();
 }
@@ -2278,11 +2294,11 @@ void launch_pass_codes(const BatchPlan* p, int pass, int step, const BatchArgs& 
     const size_t lds = p->pass_lds[pass][v];
     TraceScope ts_(rag_name(pass, v), 0, hs);
     switch (pass) {
-        case PASS_A: launch_rag<PASS_A>(v, grid, lds, hs, a, c, step); break;
-        case PASS_B: launch_rag<PASS_B>(v, grid, lds, hs, a, c, step); break;
-        case PASS_C: launch_rag<PASS_C>(v, grid, lds, hs, a, c, step); break;
-        case PASS_D: launch_rag<PASS_D>(v, grid, lds, hs, a, c, step); break;
-        default: launch_rag<PASS_E>(v, grid, lds, hs, a, c, step); break;
+        case PASS_A: launch_rag<PASS_A>(v, grid, lds, hs, a, c, step, ts_); break;
+        case PASS_B: launch_rag<PASS_B>(v, grid, lds, hs, a, c, step, ts_); break;
+        case PASS_C: launch_rag<PASS_C>(v, grid, lds, hs, a, c, step, ts_); break;
+        case PASS_D: launch_rag<PASS_D>(v, grid, lds, hs, a, c, step, ts_); break;
+        default: launch_rag<PASS_E>(v, grid, lds, hs, a, c, step, ts_); break;
     }
 }
 
@@ -2335,7 +2351,7 @@ int loop_batch_load(const void* plan, const double* uhat_pool, void* ws, size_t 
     if (st) return st;
     if (!aligned(uhat_pool, 16)) return LOOP_EINVAL;
     TraceScope ts_("k_to_band_batch", 0, (hipStream_t)stream);
-    hipLaunchKernelGGL(k_to_band_batch, dim3((p->max_nb + 31) / 32, (p->max_c + 31) / 32, p->nloops), dim3(256), 0,
+    ts_.launch(k_to_band_batch, dim3((p->max_nb + 31) / 32, (p->max_c + 31) / 32, p->nloops), dim3(256), 0,
                        (hipStream_t)stream, p->d_loops, reinterpret_cast<const cd*>(uhat_pool), static_cast<char*>(ws));
     return last_error();
 }
@@ -2347,7 +2363,7 @@ int loop_batch_store(const void* plan, double* uhat_pool, void* ws, size_t ws_by
     if (st) return st;
     if (!aligned(uhat_pool, 16)) return LOOP_EINVAL;
     TraceScope ts_("k_from_band_batch", 0, (hipStream_t)stream);
-    hipLaunchKernelGGL(k_from_band_batch, dim3((p->max_n + 31) / 32, (p->max_h + 31) / 32, p->nloops), dim3(256), 0,
+    ts_.launch(k_from_band_batch, dim3((p->max_n + 31) / 32, (p->max_h + 31) / 32, p->nloops), dim3(256), 0,
                        (hipStream_t)stream, p->d_loops, static_cast<const char*>(ws), reinterpret_cast<cd*>(uhat_pool));
     return last_error();
 }
@@ -2385,7 +2401,7 @@ int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau,
             if (total >= (1ll << 31)) return LOOP_EINVAL;
             hipLaunchKernelGGL(k_batch_reset, dim3((p->nloops + 255) / 256), dim3(256), 0, hs, a.q, a.done, p->nloops);
             TraceScope ts_("k_batch", 0, hs);
-            hipLaunchKernelGGL(k_batch, dim3(p->grid), dim3(kBlock), p->lds_bytes, hs, a);
+            ts_.launch(k_batch, dim3(p->grid), dim3(kBlock), p->lds_bytes, hs, a);
         } else if (p->schedule == LOOP_BATCH_STREAMS) {
             if ((st = launch_streams(p, nsteps, a, hs))) return st;
         } else {

@@ -73,18 +73,20 @@ def summarize_trace(stats_csv: str, out_md: str, workload: str, command: str) ->
                      f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
     trace_csv = stats_csv.replace("kernel_stats", "kernel_trace")
     if trace_csv != stats_csv and os.path.exists(trace_csv):
-        lines += _per_grid(trace_csv, [short_name(r["Name"]) for r in rows[:4]])
+        lines += _per_grid(trace_csv, [short_name(r["Name"]) for r in rows if short_name(r["Name"]).startswith("k_")])
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
 def _per_grid(trace_csv: str, kernels) -> list:
     """Launch durations of the given kernels, split by grid size: a kernel launched over all
-    loops and over groups of them (the streams schedule) has one row per grid."""
+    loops, over groups of them (the streams schedule) or over one loop (the plain method) has one
+    row per grid, so that the launches over all loops can be read apart."""
     acc = collections.defaultdict(list)
     for r in csv.DictReader(open(trace_csv)):
         k = short_name(r["Kernel_Name"])
         if k in kernels:
-            acc[(k, int(r["Grid_Size_X"]))].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+            acc[(k, int(r["Grid_Size_X"]) * int(r.get("Grid_Size_Y", 1) or 1))].append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     lines = ["", "Per grid size (work-items), from the kernel trace of the same run:", "",
              "| kernel | grid | launches | avg us | min us | max us |", "|---|---:|---:|---:|---:|---:|"]
     for (k, g), v in sorted(acc.items(), key=lambda kv: (kernels.index(kv[0][0]), -kv[0][1])):

@@ -264,3 +264,32 @@ def test_update_grad_equals_loop_update(ag):
         assert torch.equal(T1, T2)
 
 
+
+
+def test_trace_reports_each_kernel_within_the_elapsed_time(ag):
+    """api.trace over one autograd step: every kernel of the step is reported with its launch
+    count, and since the events are the kernels' own start and end on one stream, the traced
+    durations sum to no more than the elapsed time of the whole region."""
+    from paper_2007_06427_amd import api
+    specs = loopgen.config_loops(5, 4)
+    L, Nx, Ns = specs[0].L, specs[0].Nx, specs[0].Ns
+    ub = api.to_band(torch.from_numpy(np.stack([s.uhat for s in specs])).to(DEV))
+    T = torch.tensor([s.T for s in specs], dtype=torch.float64, device=DEV)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with api.trace() as tr:
+        e0.record()
+        for _ in range(3):
+            ua = ub.detach().requires_grad_(True)
+            Ta = T.detach().requires_grad_(True)
+            ag.LoopCostBand.apply(ua, Ta, L, Nx, Ns).sum().backward()
+            api.loop_update_grad(ub, T, L, ua.grad, Ta.grad, 5e-5, api.IMEX, layout=api.LAYOUT_BAND, grid=(Nx, Ns))
+        e1.record()
+        torch.cuda.synchronize()
+    names = [f"k_colA<{Ns}>", f"k_rowB<{Nx}>", f"k_colC<{Ns}, 0>", "k_finalize", f"k_colAC<{Ns}>", f"k_rowD<{Nx}>",
+             f"k_colE<{Ns}, 4>", "k_update_grad_band", "k_update_T"]
+    for n in names:
+        k = tr.kernels[n]
+        assert k["launches"] == 3 and 0.0 < k["min_us"] <= k["avg_us"] <= k["max_us"]
+    total = sum(k["total_us"] for k in tr.kernels.values())
+    assert total <= e0.elapsed_time(e1) * 1e3
