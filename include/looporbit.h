@@ -227,7 +227,9 @@ int loop_extrapolate(int Nx, int Ns, int nloops, double* T, double* uhat, const 
  * at a time, examining J of every loop on the state after each stride (and the initial one),
  * until J < J_tol for every loop or max_steps steps. With `accelerate`, each loop also
  * alternates with linear extrapolations along its trajectory: the first interval starts at
- * the first examined state with sqrt(J) <= sqrtJ_first (the paper: 1e-3); an interval ends at
+ * the first examined state with sqrt(J) <= sqrtJ_first (J = 1/2 int int r^2, half the paper's J:
+ * the paper's start, sqrt(J_paper) <= 1e-3, is sqrtJ_first = 1e-3 / sqrt(2); the tests and the
+ * oracle use 1e-3, i.e. sqrt(J_paper) <= sqrt(2) 1e-3); an interval ends at
  * the first examined state with sqrt(J) at most half its value at the interval's start, and
  * the loop is then replaced by l_b + rho/(1 - rho) (l_b - l_a), rho = sqrt(J_b / J_a), from the
  * interval's end states l_a, l_b; the next interval starts at the extrapolated state.

@@ -19,6 +19,11 @@ The appendix gives no formula; the readings taken here:
   each later one starts at the extrapolated state. An interval ends at the first examined
   state whose sqrt(J) is at most half the value at its start, and the extrapolation is made
   from the interval's two end states.
+* Which J. J here is half the paper's (J = 1/2 int int r^2), and both thresholds are applied
+  to sqrt of this J. The halving test and rho are ratios, so the factor drops out of them.
+  The start test sqrt(J) <= sqrtJ_first is the paper's sqrt(J_paper) <= 1e-3 when
+  sqrtJ_first = 1e-3 / sqrt(2); the default 1e-3 starts a little later, at
+  sqrt(J_paper) <= sqrt(2) 1e-3. The device driver (loop_converge) takes the same argument.
 * Examination. J is examined on the state after every `stride` steps (and on the initial
   state), so that a device implementation that runs `stride` steps per launch takes the same
   decisions. The run stops at the first examined state with J < J_tol, or after max_steps.
