@@ -230,11 +230,11 @@ __device__ __forceinline__ void row_pass_X(const Shape& sh, int block, const Wor
         if (idx < nout) {
             const int pp = pw0 + idx / (2 * sh.C);
             const int rem = idx % (2 * sh.C);
-            const int j = rem >> 1;
+            const int j = rem % sh.C;
             const cd* e2 = lds + XRowG<M>::EX + pp * xlen<M>();
             const cd a = e2[xpos(j)];
             const cd b = e2[xpos((M - j) & (M - 1))];
-            outv[i] = (rem & 1) ? cd{(a.y + b.y) * s, (b.x - a.x) * s} : cd{(a.x + b.x) * s, (a.y - b.y) * s};
+            outv[i] = rem >= sh.C ? cd{(a.y + b.y) * s, (b.x - a.x) * s} : cd{(a.x + b.x) * s, (a.y - b.y) * s};
         }
     }
     __syncthreads();  // every wave is done with the input tiles: the output tile overwrites tA
@@ -244,7 +244,8 @@ __device__ __forceinline__ void row_pass_X(const Shape& sh, int block, const Wor
         if (idx < nout) {
             const int pp = pw0 + idx / (2 * sh.C);
             const int rem = idx % (2 * sh.C);
-            lds[(rem >> 1) * G::TS + ((rem & 1) ? G::P + pp : pp)] = outv[i];
+            // consecutive lanes write consecutive j of one row (row b after row a)
+            lds[(rem % sh.C) * G::TS + (rem >= sh.C ? G::P + pp : pp)] = outv[i];
         }
     }
     __syncthreads();

@@ -616,15 +616,16 @@ __device__ __forceinline__ void row_forward_split(const Shape& sh, cd* va, cd* l
         if (idx < nout) {
             const int pp = pw0 + idx / (2 * G::CMAX);
             const int rem = idx % (2 * G::CMAX);
-            const int j = rem >> 1;
+            const int j = rem % G::CMAX;
+            const bool rb = rem >= G::CMAX;  // row b (else row a) of the pair
             const cd* e2 = lds + pp * xlen<M>();
             const cd a = e2[xpos(j)];
             const cd b = e2[xpos((M - j) & (M - 1))];
             if constexpr (DX) {
                 const double c = hq * j;
-                outv[i] = (rem & 1) ? cd{c * (a.x - b.x), c * (a.y + b.y)} : cd{c * (b.y - a.y), c * (a.x + b.x)};
+                outv[i] = rb ? cd{c * (a.x - b.x), c * (a.y + b.y)} : cd{c * (b.y - a.y), c * (a.x + b.x)};
             } else {
-                outv[i] = (rem & 1) ? cd{(a.y + b.y) * s, (b.x - a.x) * s} : cd{(a.x + b.x) * s, (a.y - b.y) * s};
+                outv[i] = rb ? cd{(a.y + b.y) * s, (b.x - a.x) * s} : cd{(a.x + b.x) * s, (a.y - b.y) * s};
             }
         }
     }
@@ -635,7 +636,8 @@ __device__ __forceinline__ void row_forward_split(const Shape& sh, cd* va, cd* l
         if (idx < nout) {
             const int pp = pw0 + idx / (2 * G::CMAX);
             const int rem = idx % (2 * G::CMAX);
-            lds[(rem >> 1) * G::TS + ((rem & 1) ? G::P + pp : pp)] = outv[i];
+            // consecutive lanes write consecutive j of one row: stride TS, no bank conflicts
+            lds[(rem % G::CMAX) * G::TS + (rem >= G::CMAX ? G::P + pp : pp)] = outv[i];
         }
     }
     __syncthreads();
