@@ -293,3 +293,62 @@ def test_trace_reports_each_kernel_within_the_elapsed_time(ag):
         assert k["launches"] == 3 and 0.0 < k["min_us"] <= k["avg_us"] <= k["max_us"]
     total = sum(k["total_us"] for k in tr.kernels.values())
     assert total <= e0.elapsed_time(e1) * 1e3
+
+
+def test_trace_of_batched_passes(ag):
+    """The batched passes' launches (k_rag<PASS, V>) are traced the same way: per-pass
+    schedule, two steps, four pass launches per step after the first pass A, each within the
+    elapsed time of the region."""
+    from paper_2007_06427_amd import api
+    specs = loopgen.config_loops(4, 16)
+    b = api.Batch([(s.L, s.Nx, s.Ns) for s in specs])
+    b.set_schedule(api.Batch.PER_PASS)
+    pool = b.pack([torch.from_numpy(s.uhat) for s in specs])
+    T = torch.tensor([s.T for s in specs], dtype=torch.float64, device=DEV)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with api.trace() as tr:
+        e0.record()
+        b.step(pool, T, 5e-5, api.IMEX, 2)
+        e1.record()
+        torch.cuda.synchronize()
+    rag = {k: v for k, v in tr.kernels.items() if k.startswith("k_rag<")}
+    per_pass = {}
+    for k, v in rag.items():
+        per_pass[k.split(",")[0]] = per_pass.get(k.split(",")[0], 0) + v["launches"]
+    assert per_pass == {"k_rag<0": 1, "k_rag<1": 2, "k_rag<2": 2, "k_rag<3": 2, "k_rag<4": 2}, per_pass
+    assert all(0.0 < v["min_us"] <= v["max_us"] for v in rag.values())
+    assert sum(v["total_us"] for v in tr.kernels.values()) <= e0.elapsed_time(e1) * 1e3
+
+
+def test_autograd_path_at_full_size_sampled(ag):
+    """The benchmark's own configuration: 64 loops of 256 x 1024, L = 100, band-layout state,
+    two steps of LoopCostBand forward, the reverse pass and loop_update_grad (IMEX,
+    dtau = 5e-5). J of every loop at both steps and the state and period of loops 0, 21, 42 and
+    63 after two steps against the oracle's steps, to 1e-12."""
+    from paper_2007_06427_amd import api
+    specs = loopgen.config_loops(5)
+    L, Nx, Ns = specs[0].L, specs[0].Nx, specs[0].Ns
+    u0 = np.stack([s.uhat for s in specs])
+    T0 = np.array([s.T for s in specs])
+    ub = api.to_band(torch.from_numpy(u0).to(DEV))
+    T = torch.from_numpy(T0.copy()).to(DEV)
+    Js = []
+    for _ in range(2):
+        ua = ub.detach().requires_grad_(True)
+        Ta = T.detach().requires_grad_(True)
+        J = ag.LoopCostBand.apply(ua, Ta, L, Nx, Ns)
+        J.sum().backward()
+        Js.append(J.detach().cpu().numpy())
+        api.loop_update_grad(ub, T, L, ua.grad, Ta.grad, 5e-5, api.IMEX, layout=api.LAYOUT_BAND, grid=(Nx, Ns))
+    ug = api.from_band(ub, Nx, Ns).cpu().numpy()
+    Tg = T.cpu().numpy()
+    assert np.all(np.isfinite(ug)) and np.all(Tg > 0)
+    for i in range(len(specs)):
+        Jo = K.cost(u0[i], T0[i], L)
+        assert abs(Js[0][i] - Jo) <= 1e-12 * Jo
+    for i in (0, 21, 42, 63):
+        uo, To, Jh = K.step(u0[i], T0[i], L, 5e-5, K.IMEX, 2)
+        assert wrel(ug[i], uo) < 1e-12, (i, wrel(ug[i], uo))
+        assert abs(Tg[i] - To) <= 1e-12 * To
+        assert np.allclose([Js[0][i], Js[1][i]], Jh, rtol=1e-12, atol=0)
