@@ -441,9 +441,10 @@ class Batch:
         return {"schedule": name, "variants": {n: int(v[i]) for i, n in enumerate(self.PASS_NAMES)}}
 
     def autotune(self, pool, T, reps=20) -> dict:
-        """Time every usable kernel variant of every pass and every schedule on this state
-        (pool and T are left unchanged) and keep the fastest (see loop_batch_autotune).
-        Returns the timings in microseconds and the chosen configuration."""
+        """Time every usable kernel variant of every pass, then the per-pass and the streams
+        schedules, on this state (pool and T are left unchanged) and keep the fastest (see
+        loop_batch_autotune; the persistent schedule is not timed). Returns the timings in
+        microseconds and the chosen configuration."""
         self._check_state(pool, T)
         n = 5 * self.VARIANTS + 5
         rep = (ctypes.c_double * n)()
