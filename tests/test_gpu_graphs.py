@@ -2,8 +2,9 @@
 or records a memset): one captured call replayed three times, with unrelated eager work and
 synchronisations between the replays, gives exactly the result of three eager calls.
 
-Covered: loop_step in its resident and per-pass forms, loop_step_xi, loop_step_expanded and
-ks_integrate (the batched schedules are covered in test_gpu_batch.py)."""
+Covered: loop_step in its resident and per-pass forms, loop_step_xi, loop_step_expanded,
+ks_integrate, and the reverse-mode step's three calls (loop_cost_fwd, loop_cost_bwd,
+loop_update_grad) in both layouts (the batched schedules are covered in test_gpu_batch.py)."""
 import numpy as np
 import pytest
 
@@ -93,3 +94,29 @@ def test_ks_integrate(api):
              torch.zeros(8, 10, 33, dtype=torch.complex128, device=DEV)) for _ in range(2)]
     replay_equals_eager(lambda st: il.ks_integrate(st[0], 39.0, 0.05, 40, 4, True, st[1], st[2]),
                         (u0.clone(), *bufs[0]), (u0.clone(), *bufs[1]))
+
+
+@pytest.mark.parametrize("layout", ["rfft", "band"])
+def test_reverse_mode_step(api, layout):
+    """One step of the autograd path as its three library calls: the forward (J, dJ/dT, the
+    saved residual), the reverse pass (the gradient) and the update from the gradient."""
+    Nx, Ns, L = 64, 256, 39.0
+    u, T = loops(Nx, Ns, 2, seed=17)
+    band = layout == "band"
+    kw = {"layout": api.LAYOUT_BAND, "grid": (Nx, Ns)} if band else {}
+    x = api.to_band(u) if band else u
+    ws_e = api.Workspace(api.workspace_bytes(Nx, Ns, 2))
+    ws_g = api.Workspace(api.workspace_bytes(Nx, Ns, 2))
+    Je = torch.zeros(2, dtype=torch.float64, device=DEV)
+    Jg = torch.zeros(2, dtype=torch.float64, device=DEV)
+
+    def call(st):
+        x, T, Jout = st
+        ws = ws_e if Jout is Je else ws_g
+        J, dJdT, rs = api.loop_cost_fwd(x, T, L, ws=ws, **kw)
+        gu, gT = api.loop_cost_bwd(x, T, L, rs, dJdT, None, ws=ws, **kw)
+        api.loop_update_grad(x, T, L, gu, gT, 5e-5, api.IMEX, **kw)
+        Jout.copy_(J)
+
+    replay_equals_eager(call, (x.clone(), T.clone(), Je), (x.clone(), T.clone(), Jg))
+    assert ws_g.status() == 0
