@@ -2,7 +2,8 @@
 the oracle finishes in seconds):
 
 * loop_residual, loop_cost, loop_adjoint_grad and loop_step at Nx = Ns = 1024, the largest
-  shape of the uniform entry points;
+  shape of the uniform entry points, and the reverse mode (loop_cost_fwd / loop_cost_bwd, with
+  and without the kept u, both layouts) there and at the smallest shape, 8 x 8;
 * a ragged batch holding the largest (512 x 1024) and the smallest (8 x 8) shapes a plan
   takes, with the two mixed extremes 8 x 1024 and 512 x 8;
 * loop_step_xi and loop_expanded_grad at 512 x 1024, their largest shape.
@@ -137,3 +138,35 @@ def test_expanded_grad_at_512x1024(api):
         assert wrel(G[i], Go) < TOL
         assert abs(dT[i] - dTo) <= TOL * dT_scale(u[i], T[i], L)
         assert abs(J[i] - Jo) <= TOL * Jo
+
+
+@pytest.mark.parametrize("Nx,Ns", [(1024, 1024), (8, 8), (16, 1024)])
+def test_reverse_mode_at_the_extremes(api, Nx, Ns):
+    """The reverse pass in both layouts, with and without the forward's u on the s grid,
+    gives -gJ w_j L G_1 of loop_adjoint_grad bit for bit and the oracle's gradient to 1e-12."""
+    rng = np.random.default_rng(Nx + Ns)
+    L = 300.0 if Nx == 1024 else 22.0
+    u = np.stack([loopgen.random_band_field(rng, Nx, Ns, scale=0.2) for _ in range(2)])
+    T = np.array([37.0, 71.0])
+    print(f"{Nx} x {Ns}, L = {L}, 2 loops", flush=True)
+    ud, Td = torch.from_numpy(u).to(DEV), torch.from_numpy(T).to(DEV)
+    gJ = torch.tensor([1.0, -0.5], dtype=torch.float64, device=DEV)
+    G, dJdT, J = api.loop_adjoint_grad(ud, Td, L)
+    w = torch.full((u.shape[-1],), 2.0, dtype=torch.float64, device=DEV)
+    w[0] = 1.0
+    want = -(gJ[:, None, None] * L) * w * G
+    for layout in ("rfft", "band"):
+        kw = {"layout": api.LAYOUT_BAND, "grid": (Nx, Ns)} if layout == "band" else {}
+        x = api.to_band(ud) if layout == "band" else ud
+        for keep in (False, True):
+            us = api.saved_u(2, Nx, Ns, DEV) if keep else None
+            J2, dJdT2, rs = api.loop_cost_fwd(x, Td, L, usave=us, **kw)
+            gu, gT = api.loop_cost_bwd(x, Td, L, rs, dJdT2, gJ, usave=us, **kw)
+            assert torch.equal(J2, J) and torch.equal(dJdT2, dJdT), (layout, keep)
+            g = api.from_band(gu, Nx, Ns) if layout == "band" else gu
+            assert torch.equal(g, want), (layout, keep)
+            assert torch.equal(gT, gJ * dJdT)
+    Gn = G.cpu().numpy()
+    for i in range(2):
+        Go, dTo, Jo = K.adjoint_grad(u[i], T[i], L)
+        assert wrel(Gn[i], Go) < TOL
