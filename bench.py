@@ -943,11 +943,23 @@ def bench_dns(args, E=4096, Nx=64, L=39.0, dt=0.05, every=2):
     print(json.dumps(out))
 
 
+def host_cpu() -> str:
+    """The host CPU's model name, as /proc/cpuinfo gives it (or 'unknown')."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(specs, dtau, scheme, budget_s=15.0):
     """The FP64 CPU oracle, as it stands, on a bounded sample of the same workload: rounds of
     one step of every loop of the workload, in order, until the time budget is spent."""
     pts, dt, rounds = _oracle_rounds([(s.L, s.Nx, s.Ns, s.T, s.uhat) for s in specs], dtau, scheme, budget_s)
-    return {"value": pts / dt, "unit": "pts/s", "cores": 1, "kind": "oracle",
+    return {"value": pts / dt, "unit": "pts/s", "cores": 1, "kind": "oracle", "cpu": host_cpu(),
             "sample": f"{pts} space-time points in {dt:.1f} s: {rounds} round(s) of one step of each of the "
                       f"{len(specs)} loops, in order (NumPy FP64, one process, one thread)"}
 
@@ -988,7 +1000,7 @@ def cpu_baseline_all_cores(specs, dtau, scheme, budget_s=15.0, cores=None):
         t0 = time.perf_counter()
         pts = sum(pool.map(_oracle_worker, jobs))
         dt = time.perf_counter() - t0
-    return {"value": pts / dt, "unit": "pts/s", "cores": cores, "kind": "oracle",
+    return {"value": pts / dt, "unit": "pts/s", "cores": cores, "kind": "oracle", "cpu": host_cpu(),
             "sample": f"{pts} space-time points in {dt:.1f} s: rounds of one step of each loop, the loops "
                       f"dealt over {cores} processes (NumPy FP64, one thread each)"}
 
