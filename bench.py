@@ -244,6 +244,49 @@ def main():
                 "step_achieved": round(step_bytes / (e0.elapsed_time(e1) * 1e-3 / steps) / 1e9, 1),
                 "step_frac": round(step_bytes / (e0.elapsed_time(e1) * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS, 4)}
 
+    # ---- context for the schedule choice (same loops, min(K, 500) steps each, not the headline):
+    # all steps in one persistent launch, and the tuned schedule's steps recorded once into a
+    # HIP graph and replayed
+    kc = min(steps, 500)
+
+    def gpu_ms_per_step(fn):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / kc
+
+    tuned = batch.config()["schedule"]
+    batch.set_schedule(api.Batch.PERSISTENT)
+    pool, T = pool0.clone(), T0.clone()
+    batch.step(pool, T, dtau, scheme, 2)
+    persistent_ms = gpu_ms_per_step(lambda: batch.step(pool, T, dtau, scheme, kc))
+    assert batch.status() == 0
+    if tuned.startswith("streams"):
+        batch.set_schedule(api.Batch.STREAMS, int(tuned.split("-")[1]))
+    else:
+        batch.set_schedule(api.Batch.PER_PASS)
+    pool, T = pool0.clone(), T0.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        batch.step(pool, T, dtau, scheme, 2)  # first call off the graph
+    stream.wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.step(pool, T, dtau, scheme, kc)
+    graph.replay()
+    graph_ms = gpu_ms_per_step(graph.replay)
+    assert batch.status() == 0 and bool(torch.isfinite(T).all())
+    schedules = {"tuned": tuned, "steps": kc, "tuned_eager_ms_per_step": round(e0.elapsed_time(e1) / steps, 5),
+                 "persistent_ms_per_step": round(persistent_ms, 5),
+                 "tuned_graph_replay_ms_per_step": round(graph_ms, 5),
+                 "method": "persistent: loop_batch_step with LOOP_BATCH_PERSISTENT, one launch for all steps; "
+                           "graph: the tuned schedule's loop_batch_step call of all steps recorded into a "
+                           "HIP graph (torch.cuda.CUDAGraph) and replayed"}
+
     # ---- plain method on the same loops: loop_step per loop, one after another
     plain = None
     if nl > 1:
@@ -279,6 +322,7 @@ def main():
         "gpu_ms_per_step": e0.elapsed_time(e1) / steps,
         "roofline": roofline, "cpu_baseline": cpu, "cpu_baseline_all_cores": cpu_all, "plain": plain,
         "autotune": {"pass_us": tuning["pass_us"], "step_us": tuning["step_us"]},
+        "schedules": schedules,
         "batched_vs_plain": (value / plain["value"]) if plain else None,
         "J_first_last": [float(J[0].mean()), float(J[-1].mean())],
     }
