@@ -79,3 +79,19 @@ def test_autograd_kernels_add_up_to_their_step_model():
         W, S = bench.band(Nx, Ns)
         kb = bench.autograd_kernel_bytes(Nx, Ns)
         assert len(kb) == 7 and sum(kb.values()) == 16 * (10 * W + 10 * S)
+
+
+def test_autograd_byte_model_agrees_with_the_measured_traffic():
+    """Each kernel of the autograd step (launches over all 64 loops of 256 x 1024) moves, by
+    FETCH_SIZE + WRITE_SIZE, within 5% of its algorithmic bytes (autograd_kernel_bytes), and
+    the save_u path's k_colR too (16 (S + W) per loop)."""
+    d = json.load(open(os.path.join(ROOT, "profiles", "traffic_autograd-256x1024.json")))
+    assert abs(d["copy_calibration"]["write_kib"] - 65536.0) < 1.0
+    specs = loopgen.config_loops(bench.WORKLOADS["autograd-256x1024"])
+    Nx, Ns, nl = specs[0].Nx, specs[0].Ns, len(specs)
+    W, S = bench.band(Nx, Ns)
+    want = {k: v * nl for k, v in bench.autograd_kernel_bytes(Nx, Ns).items()}
+    want[f"k_colR<{Ns}>"] = 16 * (S + W) * nl
+    for name, alg in want.items():
+        got = d["kernels"][name]["bytes_per_launch"]
+        assert abs(got / alg - 1.0) < 0.05, (name, got, alg)
