@@ -218,7 +218,7 @@ __device__ __forceinline__ void row_pass_X(const Shape& sh, int block, const Wor
     fft<M, PT, false>(acc, t, ex, twc);
 #pragma unroll
     for (int m = 0; m < PT; ++m) ex[xpos(t + m * G::TPF)] = acc[m];
-    wave_lds_sync();
+    wave_lds_order();
     const int lane = threadIdx.x % 64;
     const int pw0 = (threadIdx.x / 64) * G::PW;
     const int nout = 2 * G::PW * sh.C;

@@ -258,16 +258,19 @@ __device__ __forceinline__ void apply_twiddles(cd* v, int i, const cd* base) {
     }
 }
 
-// Wavefront-level LDS ordering: wait until this wave's LDS accesses are done, and keep the
-// compiler from moving memory operations across this point.
-__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// Wavefront-level LDS ordering. The LDS performs the operations of one wavefront in the order
+// they were issued, so a read issued after a write of the same wavefront returns what the
+// write stored, for every lane, without waiting for the write to complete (a wait is needed
+// only between wavefronts). Only the compiler has to keep the order: no memory operation
+// moves across this point. Read results are waited for where they are used.
+__device__ __forceinline__ void wave_lds_order() { asm volatile("" ::: "memory"); }
 
-// Ordering between stages: a wavefront barrier when the transform fits in one wavefront,
+// Ordering between stages: wavefront order when the transform fits in one wavefront,
 // otherwise a block barrier (every thread of the block then runs the same transform code).
 template <int TPF>
 __device__ __forceinline__ void xsync() {
     if constexpr (TPF <= 64) {
-        wave_lds_sync();
+        wave_lds_order();
     } else {
         __syncthreads();
     }

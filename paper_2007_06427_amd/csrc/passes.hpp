@@ -606,7 +606,7 @@ __device__ __forceinline__ void row_forward_split(const Shape& sh, cd* va, cd* l
     fft<M, G::PT, false>(va, t, ex, twc);
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) ex[xpos(t + m * G::TPF)] = va[m];
-    wave_lds_sync();
+    wave_lds_order();
     const int lane = threadIdx.x % 64;
     const int pw0 = (threadIdx.x / 64) * G::PW;
     constexpr int nout = 2 * G::PW * G::CMAX;

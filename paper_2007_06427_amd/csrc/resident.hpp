@@ -83,7 +83,7 @@ __device__ __forceinline__ void res_row_products(const Shape& sh, cd* va, cd* vb
     fft<M, G::PT, false>(va, t, ex, twc);
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) ex[xpos(t + m * G::TPF)] = va[m];
-    wave_lds_sync();
+    wave_lds_order();
     const double s = 0.5 / M;
     for (int j = t; j < sh.C; j += G::TPF) {
         const cd za = ex[xpos(j)];
@@ -91,7 +91,7 @@ __device__ __forceinline__ void res_row_products(const Shape& sh, cd* va, cd* vb
         if (oka) X[j * sh.N + a] = cd{(za.x + zb.x) * s, (za.y - zb.y) * s};
         if (okb) X[j * sh.N + b] = cd{(za.y + zb.y) * s, (zb.x - za.x) * s};
     }
-    wave_lds_sync();  // the exchange region is reused by this group's next transform
+    wave_lds_order();  // the exchange region is reused by this group's next transform
 }
 
 // Pass B for the pairs of row tile `tile`: X = (u u_x) = (1/2) (u^2)_x per row, from A (the
@@ -119,7 +119,7 @@ __device__ __forceinline__ void res_row_B(const Shape& sh, int tile, const cd* A
     fft<M, G::PT, false>(va, ln.t, ex, twc);
 #pragma unroll
     for (int m = 0; m < G::PT; ++m) ex[xpos(ln.t + m * G::TPF)] = va[m];
-    wave_lds_sync();
+    wave_lds_order();
     const double hq = (kTwoPi / sh.L) * (0.25 / M);
     for (int j = ln.t; j < sh.C; j += G::TPF) {
         const cd za = ex[xpos(j)];
@@ -128,7 +128,7 @@ __device__ __forceinline__ void res_row_B(const Shape& sh, int tile, const cd* A
         if (oka) X[j * sh.N + a] = cd{c * (zb.y - za.y), c * (za.x + zb.x)};
         if (okb) X[j * sh.N + b] = cd{c * (za.x - zb.x), c * (za.y + zb.y)};
     }
-    wave_lds_sync();  // the exchange region is reused by this group's next transform
+    wave_lds_order();  // the exchange region is reused by this group's next transform
 }
 
 // Pass D for the pairs of row tile `tile`: X = (u r_x) per row, from A and X (r_x), in place.
