@@ -48,7 +48,7 @@ extern "C" {
 typedef enum {
     LOOP_OK = 0,
     LOOP_EINVAL = -1,      /* bad size, pointer, alignment, L, dtau or scheme */
-    LOOP_ENOTSUP = -2,     /* a size the library does not support (e.g. Nx not a power of two) */
+    LOOP_ENOTSUP = -2,     /* a size or device the library does not support (e.g. Nx not a power of two) */
     LOOP_EHIP = -3,        /* a HIP runtime call failed */
     LOOP_ENONFINITE = -4,  /* device saw T <= 0 or a non-finite T or J (sticky, see loop_status_sync) */
     LOOP_EWORKSPACE = -5,  /* work space too small or not prepared by loop_workspace_init */
@@ -287,9 +287,12 @@ typedef enum { LOOP_BATCH_PER_PASS = 0, LOOP_BATCH_PERSISTENT = 1, LOOP_BATCH_ST
 int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns, void** plan);
 /* Choose how loop_batch_step runs the steps (results are identical bit for bit):
  *   LOOP_BATCH_PER_PASS (default): one kernel per pass over every loop's tiles, four per step;
- *   LOOP_BATCH_PERSISTENT: one launch for all steps, blocks pulling (pass, loop, tile) items
- *   in dependency order (see the scheduler notes in the source); it measured 3-5x slower than
- *   the other two, and loop_batch_autotune does not choose it;
+ *   LOOP_BATCH_PERSISTENT: one launch for all steps. Each loop is assigned to one XCD, and
+ *   blocks pull (pass, loop, tile) items of their own XCD's list in dependency order, so that
+ *   every hand-over between blocks stays within one L2 (see the scheduler notes in the
+ *   source). A block on an XCD the device does not report (hipDeviceAttributeNumberOfXccs)
+ *   leaves and sets LOOP_ENOTSUP. It measured 1.5-2.5x slower than the other two, and
+ *   loop_batch_autotune does not choose it;
  *   LOOP_BATCH_STREAMS: the loops split into K groups of about equal work (K from
  *   loop_batch_set_streams, 2 to 4, default 2), group 0 on `stream` and the others on streams
  *   the plan owns (default priority), each started one pass after the previous group, so that

@@ -429,21 +429,31 @@ __global__ void k_ws_clear_status(WsHeader* h) { h->status = 0; }
 __global__ void k_copy_status(const WsHeader* h, int* status) { *status = h->status; }
 
 // ============================================================================ batched scheduler
-// A batch of loops of uneven shape advances in one persistent launch. The launch works
-// through a fixed, totally ordered list of items (pass, loop, tile):
-//   the A tiles of every loop, then for each step the B, C, D and E tiles of every loop.
-// Blocks take items in list order from a global counter. Before an item of loop l runs, its
-// block waits until loop l's completion counter shows that every earlier item of loop l is
-// done. Pass p of a step needs all of pass p-1, and pass B of the next step needs all of the
+// A batch of loops of uneven shape advances in one persistent launch. Each loop belongs to one
+// XCD (the chip's eight accelerator dies, each with its own L2 cache), and each XCD works
+// through a fixed, totally ordered list of its loops' items (pass, loop, tile):
+//   the A tiles of its loops, then for each step the B, C, D and E tiles of its loops.
+// A block reads the XCD it runs on from the XCC_ID hardware register and takes items of that
+// XCD's list, in order, from that list's counter. Before an item of loop l runs, its block
+// waits until loop l's completion counter shows that every earlier item of loop l is done.
+// Pass p of a step needs all of pass p-1, and pass B of the next step needs all of the
 // previous pass E (which also wrote the next pass A). An item depends only on items earlier in
-// the list, and a block that has taken an item is running. So the earliest unfinished item
-// can always proceed, and the launch cannot deadlock. Every wait is still bounded in time:
-// if one runs out, the block raises an abort flag that every other wait also checks, the
+// its list, and a block that has taken an item is running. So the earliest unfinished item of
+// each list can always proceed, and the launch cannot deadlock. Every wait is still bounded in
+// time: if one runs out, the block raises an abort flag that every other wait also checks, the
 // status becomes LOOP_EHANG, and all blocks leave.
+//
+// Hand-over between blocks. Producer and consumer of a loop's tiles run on CUs of the same
+// XCD and so share its L2: the producer's stores are in that L2 once the wavefront's store
+// counter reaches zero, and the consumer invalidates its CU's L1 before it reads. No L2 is
+// written back or invalidated per item (an agent-scope release or acquire would do both, for
+// the whole L2, which costs far more than the item's work). Kernel boundaries order the launch
+// against the kernels before and after it as usual.
 //
 // The queue and completion counters live in the work space and are cleared by a small kernel
 // queued before every launch (k_batch_reset), so that a launch abandoned after a wait ran out
 // leaves nothing behind for the next one.
+constexpr int kMaxXcd = 16;
 struct WsOff {  // byte offsets of one loop's regions inside the work space
     size_t A, BD, Cb, U, G, partial, J, dJdT, Told;
 };
@@ -457,10 +467,9 @@ struct BatchLoop {
 };
 
 struct BatchQueue {
-    int next;    // next item to hand out
-    int exited;  // blocks that have left
-    int abort;   // raised when a bounded wait runs out
-    int pad;
+    int next[kMaxXcd];  // next item of each XCD's list to hand out
+    int abort;          // raised when a bounded wait runs out
+    int pad[3];
 };
 
 enum : int { PASS_A = 0, PASS_B = 1, PASS_C = 2, PASS_D = 3, PASS_E = 4 };
@@ -471,8 +480,9 @@ __host__ __device__ inline uint32_t item_code(int l, int pass, int tile) {
 
 struct BatchArgs {
     const BatchLoop* loops;
-    const uint32_t* items;  // nA prologue items, then the ips items of one step
-    int nloops, nA, ips, nsteps;
+    const uint32_t* items;  // per XCD x, from items + xoff[x]: nA[x] prologue items, then the ips[x] of one step
+    int nloops, nsteps, nxcd;
+    int xoff[kMaxXcd], nA[kMaxXcd], ips[kMaxXcd];
     BatchQueue* q;
     int* done;  // [nloops] completion counters
     char* ws;
@@ -507,11 +517,11 @@ __device__ __forceinline__ Work batch_work(const BatchLoop& b, char* ws, int* st
 // (it raises the abort flag), or another one did. Either way the status word says LOOP_EHANG,
 // so that an abandoned launch never passes for a complete one.
 __device__ int wait_count(int* cnt, int target, BatchQueue* q, int* status, unsigned long long spin_ticks) {
-    if (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) return 0;
+    if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return 0;
     const uint64_t t0 = wall_clock64();
     for (;;) {
         __builtin_amdgcn_s_sleep(2);
-        if (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) return 0;
+        if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return 0;
         if (__hip_atomic_load(&q->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
             wall_clock64() - t0 > spin_ticks) {
             atomicExch(&q->abort, 1);
@@ -521,18 +531,24 @@ __device__ int wait_count(int* cnt, int target, BatchQueue* q, int* status, unsi
     }
 }
 
-#define LO_CASE_ROW(M_, CALL) case M_: { constexpr int S_ = M_; CALL; } break;
-#define LO_ROW_SWITCH(m, CALL)                                                                       \
-    switch (m) {                                                                                     \
-        LO_CASE_ROW(8, CALL) LO_CASE_ROW(16, CALL) LO_CASE_ROW(32, CALL) LO_CASE_ROW(64, CALL)      \
-        LO_CASE_ROW(128, CALL) LO_CASE_ROW(256, CALL) LO_CASE_ROW(512, CALL) default: break;         \
+// Calls f(std::integral_constant<int, S>) for the power of two S == n in [LO, HI]; other n do
+// nothing (plans only hold sizes their kernels cover).
+template <int LO, int HI, class F>
+__device__ __forceinline__ void size_switch(int n, F&& f) {
+    if constexpr (LO <= HI) {
+        if (n == LO)
+            f(std::integral_constant<int, LO>{});
+        else
+            size_switch<2 * LO, HI>(n, static_cast<F&&>(f));
     }
-#define LO_COL_SWITCH(n, CALL)                                                                       \
-    switch (n) {                                                                                     \
-        LO_CASE_ROW(8, CALL) LO_CASE_ROW(16, CALL) LO_CASE_ROW(32, CALL) LO_CASE_ROW(64, CALL)      \
-        LO_CASE_ROW(128, CALL) LO_CASE_ROW(256, CALL) LO_CASE_ROW(512, CALL)                         \
-        LO_CASE_ROW(1024, CALL) default: break;                                                      \
-    }
+}
+
+// The twiddle table's address as seen by one pass: an opaque copy, so that the compiler does
+// not hoist every pass's twiddle cache out of the step loop and keep them all live at once.
+__device__ __forceinline__ const cd* per_pass(const cd* tw) {
+    asm volatile("" : "+s"(tw));
+    return tw;
+}
 
 // One pass body per (pass, size), each compiled as its own function so that register
 // allocation is per body rather than over the union of all bodies.
@@ -561,22 +577,34 @@ __device__ __noinline__ void bk_E(const Shape& sh, int tile, const Work& w, doub
 }
 
 __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
+    constexpr int RH = 512, CH = 1024;  // transform sizes of the batched passes
     extern __shared__ __align__(16) cd lds[];  // 16-byte aligned: one ds_read_b128 per complex value
     __shared__ double red[2 * kBlock / 64];
     __shared__ int s_item, s_stop;
-    const int total = a.nA + a.nsteps * a.ips;
+    // the XCD this block runs on (XCC_ID, bits 3:0 of hardware register 20)
+    const int x = (int)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
+    if (x >= a.nxcd) {  // not an XCD the plan knows: leave, and say so
+        if (threadIdx.x == 0) {
+            atomicExch(&a.q->abort, 1);
+            atomicCAS(a.status, 0, LOOP_ENOTSUP);
+        }
+        return;
+    }
+    const uint32_t* items = a.items + a.xoff[x];
+    const int nA = a.nA[x], ips = a.ips[x];
+    const int total = nA + a.nsteps * ips;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&a.q->next, 1);
+        if (threadIdx.x == 0) s_item = atomicAdd(&a.q->next[x], 1);
         __syncthreads();
         const int i = s_item;
         if (i >= total) break;
         int s = 0;
         uint32_t code;
-        if (i < a.nA) {
-            code = a.items[i];
+        if (i < nA) {
+            code = items[i];
         } else {
-            s = (i - a.nA) / a.ips;
-            code = a.items[a.nA + (i - a.nA) % a.ips];
+            s = (i - nA) / ips;
+            code = items[nA + (i - nA) % ips];
         }
         const int l = (int)(code >> 16), pass = (int)((code >> 13) & 7), tile = (int)(code & 0x1fff);
         const BatchLoop b = a.loops[l];
@@ -585,41 +613,42 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
             target = b.nt[PASS_A] + s * b.ipl;
             for (int p = PASS_B; p < pass; ++p) target += b.nt[p];
         }
-        // Thread 0's acquiring load of the counter invalidates this CU's L1 and this XCD's L2,
-        // so the block's loads after the barrier see the producers' written-back results.
         if (threadIdx.x == 0) s_stop = wait_count(&a.done[l], target, a.q, a.status, a.spin_ticks);
         __syncthreads();
         if (s_stop) break;
+        // The producers ran on this XCD: their results are in its L2. Drop this CU's L1 copies
+        // of earlier contents before reading (each wavefront, ahead of its own loads).
+        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
         const Work w = batch_work(b, a.ws, a.status);
         const Shape& sh = b.sh;
         switch (pass) {
             case PASS_A:
-                LO_COL_SWITCH(sh.N, bk_A<S_>(sh, tile, w, lds, a.tw));
+                size_switch<8, CH>(sh.N, [&](auto c) { bk_A<decltype(c)::value>(sh, tile, w, lds, a.tw); });
                 break;
             case PASS_B:
-                LO_ROW_SWITCH(sh.M, bk_B<S_>(sh, tile, w, lds, a.tw));
+                size_switch<8, RH>(sh.M, [&](auto c) { bk_B<decltype(c)::value>(sh, tile, w, lds, a.tw); });
                 break;
             case PASS_C:
-                LO_COL_SWITCH(sh.N, bk_C<S_>(sh, tile, a.T + l, w, a.dtau, a.scheme, lds, red, a.tw));
+                size_switch<8, CH>(sh.N, [&](auto c) {
+                    bk_C<decltype(c)::value>(sh, tile, a.T + l, w, a.dtau, a.scheme, lds, red, a.tw);
+                });
                 break;
             case PASS_D: {
                 double* jh = a.J_hist ? a.J_hist + (size_t)s * a.nloops + l : nullptr;
-                LO_ROW_SWITCH(sh.M, bk_D<S_>(sh, tile, w, a.T + l, a.dtau, jh, lds, a.tw));
+                size_switch<8, RH>(sh.M, [&](auto c) { bk_D<decltype(c)::value>(sh, tile, w, a.T + l, a.dtau, jh, lds, a.tw); });
                 break;
             }
             default:
-                LO_COL_SWITCH(sh.N, bk_E<S_>(sh, tile, w, a.dtau, a.scheme, s + 1 < a.nsteps, lds, a.tw));
+                size_switch<8, CH>(sh.N, [&](auto c) {
+                    bk_E<decltype(c)::value>(sh, tile, w, a.dtau, a.scheme, s + 1 < a.nsteps, lds, a.tw);
+                });
                 break;
         }
-        // Every wave waits until its stores have reached this XCD's L2; after the barrier one
-        // agent-scope release by thread 0 writes the L2 back, so that blocks on other XCDs
-        // can read the results, before the counter moves.
+        // Every wave waits until its stores have reached this XCD's L2; after the barrier the
+        // counter moves. Consumers run on this XCD too, so nothing is written back.
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        if (threadIdx.x == 0) {
-            __threadfence();
-            atomicAdd(&a.done[l], 1);
-        }
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(&a.done[l], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -628,11 +657,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
 // a launch abandoned after a wait ran out leaves them partly counted.
 __global__ void k_batch_reset(BatchQueue* q, int* done, int nloops) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        q->next = 0;
-        q->exited = 0;
-        q->abort = 0;
-    }
+    if (i < kMaxXcd) q->next[i] = 0;
+    if (i == 0) q->abort = 0;
     for (int l = i; l < nloops; l += gridDim.x * blockDim.x) done[l] = 0;
 }
 
@@ -667,18 +693,6 @@ __host__ __device__ constexpr RagVariant rag_variant(int pass, int v) {
 template <int M, int PT>
 constexpr int row_pt() {
     return PT ? PT : RowG<M>::PT;
-}
-
-// Calls f(std::integral_constant<int, S>) for the power of two S == n in [LO, HI]; other n do
-// nothing (plans only hold sizes their kernels cover).
-template <int LO, int HI, class F>
-__device__ __forceinline__ void size_switch(int n, F&& f) {
-    if constexpr (LO <= HI) {
-        if (n == LO)
-            f(std::integral_constant<int, LO>{});
-        else
-            size_switch<2 * LO, HI>(n, static_cast<F&&>(f));
-    }
 }
 
 template <int PASS, int V>
@@ -734,12 +748,6 @@ void launch_rag(int v, dim3 grid, size_t lds, hipStream_t hs, const BatchArgs& a
 // LDS-resident step (see resident.hpp): block l runs all nsteps of loop l with its state and
 // intermediates in LDS. The rfft-layout spectrum is read at the start and written back at
 // the end (the same arithmetic as k_to_band and k_from_band), T[l] likewise.
-// The twiddle table's address as seen by one pass: an opaque copy, so that the compiler does
-// not hoist every pass's twiddle cache out of the step loop and keep them all live at once.
-__device__ __forceinline__ const cd* per_pass(const cd* tw) {
-    asm volatile("" : "+s"(tw));
-    return tw;
-}
 
 // LDS-resident step (see resident.hpp): block l runs all nsteps of loop l with its state and
 // intermediates in LDS. The rfft-layout spectrum is read at the start and written back at
@@ -873,11 +881,8 @@ __global__ __launch_bounds__(256) void k_from_band_batch(const BatchLoop* loops,
 
 __global__ void k_batch_ws_init(BatchQueue* q, int* done, int nloops) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        q->next = 0;
-        q->exited = 0;
-        q->abort = 0;
-    }
+    if (i < kMaxXcd) q->next[i] = 0;
+    if (i == 0) q->abort = 0;
     if (i < nloops) done[i] = 0;
 }
 
@@ -1409,7 +1414,8 @@ struct BatchPlan {
     std::vector<BatchLoop> loops;
     BatchLoop* d_loops = nullptr;
     uint32_t* d_items = nullptr;
-    int nA = 0, ips = 0;
+    int nxcd = 1;                   // XCDs of the device: one item list each (persistent schedule)
+    int xoff[kMaxXcd] = {}, nA[kMaxXcd] = {}, ips[kMaxXcd] = {};
     size_t ws_bytes = 0, q_off = 0, done_off = 0, pool_elems = 0;
     int max_nb = 1, max_c = 1, max_n = 1, max_h = 1;
     size_t lds_bytes = 0;
@@ -2136,14 +2142,39 @@ int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns,
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return (size_t)p->loops[a].sh.M * p->loops[a].sh.N > (size_t)p->loops[b].sh.M * p->loops[b].sh.N;
     });
+    // persistent schedule: each loop on one XCD (larger loops placed first, each on the XCD
+    // with the fewest bytes per step so far), and one item list per XCD
+    int nxcd = 1;
+    if (hipDeviceGetAttribute(&nxcd, hipDeviceAttributeNumberOfXccs, p->device) != hipSuccess) {
+        free_plan(p);
+        return LOOP_EHIP;
+    }
+    p->nxcd = std::min(std::max(nxcd, 1), kMaxXcd);
+    std::vector<int> xcd_of(nloops, 0);
+    {
+        std::vector<size_t> load(p->nxcd, 0);
+        for (int l : order) {
+            const Shape& sh = p->loops[l].sh;
+            int g = 0;
+            for (int h = 1; h < p->nxcd; ++h)
+                if (load[h] < load[g]) g = h;
+            xcd_of[l] = g;
+            load[g] += 9 * (size_t)sh.C * sh.N + 4 * (size_t)sh.C * sh.NB;
+        }
+    }
     std::vector<uint32_t> items;
-    for (int l : order)
-        for (int t = 0; t < p->loops[l].nt[PASS_A]; ++t) items.push_back(item_code(l, PASS_A, t));
-    p->nA = (int)items.size();
-    for (int pass = PASS_B; pass <= PASS_E; ++pass)
+    for (int x = 0; x < p->nxcd; ++x) {
+        p->xoff[x] = (int)items.size();
         for (int l : order)
-            for (int t = 0; t < p->loops[l].nt[pass]; ++t) items.push_back(item_code(l, pass, t));
-    p->ips = (int)items.size() - p->nA;
+            if (xcd_of[l] == x)
+                for (int t = 0; t < p->loops[l].nt[PASS_A]; ++t) items.push_back(item_code(l, PASS_A, t));
+        p->nA[x] = (int)items.size() - p->xoff[x];
+        for (int pass = PASS_B; pass <= PASS_E; ++pass)
+            for (int l : order)
+                if (xcd_of[l] == x)
+                    for (int t = 0; t < p->loops[l].nt[pass]; ++t) items.push_back(item_code(l, pass, t));
+        p->ips[x] = (int)items.size() - p->xoff[x] - p->nA[x];
+    }
     // per-pass code lists for the launch-per-pass schedule
     std::vector<uint32_t> pcodes;
     for (int pass = PASS_A; pass <= PASS_E; ++pass) {
@@ -2259,8 +2290,12 @@ BatchArgs batch_args(const BatchPlan* p, char* base, double* T, double* J_hist, 
     a.loops = p->d_loops;
     a.items = p->d_items;
     a.nloops = p->nloops;
-    a.nA = p->nA;
-    a.ips = p->ips;
+    a.nxcd = p->nxcd;
+    for (int x = 0; x < kMaxXcd; ++x) {
+        a.xoff[x] = p->xoff[x];
+        a.nA[x] = p->nA[x];
+        a.ips[x] = p->ips[x];
+    }
     a.nsteps = nsteps;
     a.q = reinterpret_cast<BatchQueue*>(base + p->q_off);
     a.done = reinterpret_cast<int*>(base + p->done_off);
@@ -2397,8 +2432,8 @@ int loop_batch_step(const void* plan, double* T, double* uhat_pool, double dtau,
     if (nsteps > 0) {
         const BatchArgs a = batch_args(p, base, T, J_hist, nsteps, dtau, scheme, tw);
         if (p->schedule == LOOP_BATCH_PERSISTENT) {
-            const long long total = (long long)p->nA + (long long)nsteps * p->ips;
-            if (total >= (1ll << 31)) return LOOP_EINVAL;
+            for (int x = 0; x < p->nxcd; ++x)
+                if ((long long)p->nA[x] + (long long)nsteps * p->ips[x] >= (1ll << 31)) return LOOP_EINVAL;
             hipLaunchKernelGGL(k_batch_reset, dim3((p->nloops + 255) / 256), dim3(256), 0, hs, a.q, a.done, p->nloops);
             TraceScope ts_("k_batch", 0, hs);
             ts_.launch(k_batch, dim3(p->grid), dim3(kBlock), p->lds_bytes, hs, a);

@@ -128,6 +128,40 @@ def test_persistent_wait_that_runs_out_is_reported_and_the_next_launch_is_clean(
         assert np.array_equal(T.cpu().numpy(), ref[2]) and np.array_equal(Jh.cpu().numpy(), ref[3])
 
 
+@pytest.mark.parametrize("n", [1, 5, 11, 40])
+def test_persistent_schedule_equals_per_pass_for_any_number_of_loops(api, n):
+    """The persistent schedule gives each loop to one XCD and hands tiles over only inside that
+    XCD's L2; with fewer loops than XCDs some XCDs' lists are empty. Ten steps of n loops (the
+    edge shapes 8 x 1024, 512 x 16 and 16 x 8 among them) equal the per-pass schedule bit for
+    bit, periods and J history included."""
+    specs = ragged_specs(max(n - 3, 0), seed=40 + n)[:n]
+    _, u0, T0, J0 = run_batch(api, specs, 10, 5e-5, api.IMEX, 0)
+    b, u1, T1, J1 = run_batch(api, specs, 10, 5e-5, api.IMEX, 1)
+    assert b.status() == 0
+    assert all(np.array_equal(a, c) for a, c in zip(u0, u1))
+    assert np.array_equal(T0, T1) and np.array_equal(J0, J1)
+
+
+def test_persistent_schedule_over_many_steps_and_launches(api):
+    """Sixty steps of 48 loops in one launch, twice, each equal to the per-pass schedule bit for
+    bit: a tile read before its producer's stores were in the L2 its consumer reads would show
+    here."""
+    specs = ragged_specs(45, seed=5)
+    _, u0, T0, J0 = run_batch(api, specs, 60, 5e-5, api.IMEX, 0)
+    b = api.Batch([(L, Nx, Ns) for (L, Nx, Ns, T, u) in specs])
+    b.set_schedule(api.Batch.PERSISTENT)
+    pool0 = b.pack([torch.from_numpy(u) for (*_, u) in specs])
+    Tin = torch.tensor([s[3] for s in specs], dtype=torch.float64, device=DEV)
+    for _ in range(2):
+        pool, T = pool0.clone(), Tin.clone()
+        Jh = torch.zeros(60, len(specs), dtype=torch.float64, device=DEV)
+        b.step(pool, T, 5e-5, api.IMEX, 60, J_hist=Jh)
+        torch.cuda.synchronize()
+        assert b.status() == 0
+        assert all(np.array_equal(u.cpu().numpy(), w) for u, w in zip(b.unpack(pool), u0))
+        assert np.array_equal(T.cpu().numpy(), T0) and np.array_equal(Jh.cpu().numpy(), J0)
+
+
 @pytest.mark.parametrize("schedule", SCHEDULES)
 def test_batch_zero_steps_canonicalises_and_relaunches(api, schedule):
     specs = ragged_specs(4, seed=3)
