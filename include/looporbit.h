@@ -290,8 +290,9 @@ int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns,
  *   LOOP_BATCH_PERSISTENT: one launch for all steps. Each loop is assigned to one XCD, and
  *   blocks pull (pass, loop, tile) items of their own XCD's list in dependency order, so that
  *   every hand-over between blocks stays within one L2 (see the scheduler notes in the
- *   source). A block on an XCD the device does not report (hipDeviceAttributeNumberOfXccs)
- *   leaves and sets LOOP_ENOTSUP. It measured 1.5-2.5x slower than the other two, and
+ *   source). loop_batch_create finds the XCDs with a probe launch; a block on an XCD the
+ *   probe did not see leaves and sets LOOP_ENOTSUP. It measured 1.5-2.5x slower than the
+ *   other two, and
  *   loop_batch_autotune does not choose it;
  *   LOOP_BATCH_STREAMS: the loops split into K groups of about equal work (K from
  *   loop_batch_set_streams, 2 to 4, default 2), group 0 on `stream` and the others on streams

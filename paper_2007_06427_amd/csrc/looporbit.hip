@@ -481,7 +481,8 @@ __host__ __device__ inline uint32_t item_code(int l, int pass, int tile) {
 struct BatchArgs {
     const BatchLoop* loops;
     const uint32_t* items;  // per XCD x, from items + xoff[x]: nA[x] prologue items, then the ips[x] of one step
-    int nloops, nsteps, nxcd;
+    int nloops, nsteps;
+    int xlist[kMaxXcd];  // item list of the XCD with each XCC_ID, or -1 for an id the plan never saw
     int xoff[kMaxXcd], nA[kMaxXcd], ips[kMaxXcd];
     BatchQueue* q;
     int* done;  // [nloops] completion counters
@@ -529,6 +530,15 @@ __device__ int wait_count(int* cnt, int target, BatchQueue* q, int* status, unsi
             return 1;
         }
     }
+}
+
+// The XCD (accelerator die) the calling wavefront runs on: XCC_ID, bits 3:0 of hardware
+// register 20 on gfx950.
+__device__ __forceinline__ int xcc_id() { return (int)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20); }
+
+// Marks in seen[] the XCC_IDs of the XCDs that run this launch's blocks.
+__global__ void k_xcc_probe(int* seen) {
+    if (threadIdx.x == 0) seen[xcc_id()] = 1;
 }
 
 // Calls f(std::integral_constant<int, S>) for the power of two S == n in [LO, HI]; other n do
@@ -581,9 +591,9 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a) {
     extern __shared__ __align__(16) cd lds[];  // 16-byte aligned: one ds_read_b128 per complex value
     __shared__ double red[2 * kBlock / 64];
     __shared__ int s_item, s_stop;
-    // the XCD this block runs on (XCC_ID, bits 3:0 of hardware register 20)
-    const int x = (int)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
-    if (x >= a.nxcd) {  // not an XCD the plan knows: leave, and say so
+    // the list of the XCD this block runs on (XCC_ID, bits 3:0 of hardware register 20)
+    const int x = a.xlist[xcc_id()];
+    if (x < 0) {  // an XCD the plan's probe did not see: leave, and say so
         if (threadIdx.x == 0) {
             atomicExch(&a.q->abort, 1);
             atomicCAS(a.status, 0, LOOP_ENOTSUP);
@@ -1415,6 +1425,7 @@ struct BatchPlan {
     BatchLoop* d_loops = nullptr;
     uint32_t* d_items = nullptr;
     int nxcd = 1;                   // XCDs of the device: one item list each (persistent schedule)
+    int xlist[kMaxXcd] = {};        // item list of each XCC_ID, -1 for ids not seen
     int xoff[kMaxXcd] = {}, nA[kMaxXcd] = {}, ips[kMaxXcd] = {};
     size_t ws_bytes = 0, q_off = 0, done_off = 0, pool_elems = 0;
     int max_nb = 1, max_c = 1, max_n = 1, max_h = 1;
@@ -2143,13 +2154,30 @@ int loop_batch_create(int nloops, const double* L, const int* Nx, const int* Ns,
         return (size_t)p->loops[a].sh.M * p->loops[a].sh.N > (size_t)p->loops[b].sh.M * p->loops[b].sh.N;
     });
     // persistent schedule: each loop on one XCD (larger loops placed first, each on the XCD
-    // with the fewest bytes per step so far), and one item list per XCD
-    int nxcd = 1;
-    if (hipDeviceGetAttribute(&nxcd, hipDeviceAttributeNumberOfXccs, p->device) != hipSuccess) {
-        free_plan(p);
-        return LOOP_EHIP;
+    // with the fewest bytes per step so far), and one item list per XCD. The XCDs are those
+    // whose XCC_IDs a probe launch of many blocks reports (blocks are dealt to every XCD).
+    {
+        int cus = 1;
+        int* d_seen = nullptr;
+        int seen[kMaxXcd] = {};
+        const bool ok = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess &&
+                        hipMalloc((void**)&d_seen, sizeof(seen)) == hipSuccess &&
+                        hipMemcpy(d_seen, seen, sizeof(seen), hipMemcpyHostToDevice) == hipSuccess;
+        if (ok) hipLaunchKernelGGL(k_xcc_probe, dim3(16 * std::max(cus, 1)), dim3(64), 0, 0, d_seen);
+        const bool ok2 = ok && hipGetLastError() == hipSuccess &&
+                         hipMemcpy(seen, d_seen, sizeof(seen), hipMemcpyDeviceToHost) == hipSuccess;
+        if (d_seen) hipFree(d_seen);
+        if (!ok2) {
+            free_plan(p);
+            return LOOP_EHIP;
+        }
+        p->nxcd = 0;
+        for (int id = 0; id < kMaxXcd; ++id) p->xlist[id] = seen[id] ? p->nxcd++ : -1;
+        if (p->nxcd == 0) {
+            free_plan(p);
+            return LOOP_EHIP;
+        }
     }
-    p->nxcd = std::min(std::max(nxcd, 1), kMaxXcd);
     std::vector<int> xcd_of(nloops, 0);
     {
         std::vector<size_t> load(p->nxcd, 0);
@@ -2290,8 +2318,8 @@ BatchArgs batch_args(const BatchPlan* p, char* base, double* T, double* J_hist, 
     a.loops = p->d_loops;
     a.items = p->d_items;
     a.nloops = p->nloops;
-    a.nxcd = p->nxcd;
     for (int x = 0; x < kMaxXcd; ++x) {
+        a.xlist[x] = p->xlist[x];
         a.xoff[x] = p->xoff[x];
         a.nA[x] = p->nA[x];
         a.ips[x] = p->ips[x];
