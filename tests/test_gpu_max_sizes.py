@@ -6,7 +6,8 @@ the oracle finishes in seconds):
   and without the kept u, both layouts) there and at the smallest shape, 8 x 8;
 * a ragged batch holding the largest (512 x 1024) and the smallest (8 x 8) shapes a plan
   takes, with the two mixed extremes 8 x 1024 and 512 x 8;
-* loop_step_xi and loop_expanded_grad at 512 x 1024, their largest shape.
+* loop_step_xi and loop_expanded_grad at 512 x 1024, their largest shape;
+* the largest loop count, 65535 loops of 8 x 8, per loop and as a batched plan.
 
 The tolerance is that of the other parity tests: 1e-12 normwise per output and per step. dJ/dT
 is measured against the size of the terms that cancel in it, (L/T^2) ||u_s|| ||r||."""
@@ -170,3 +171,45 @@ def test_reverse_mode_at_the_extremes(api, Nx, Ns):
     for i in range(2):
         Go, dTo, Jo = K.adjoint_grad(u[i], T[i], L)
         assert wrel(Gn[i], Go) < TOL
+
+
+def test_largest_loop_count(api):
+    """65535 loops (the most one call or plan takes) of 8 x 8: one IMEX step of every loop by
+    loop_step, and the same loops as a batched plan (a loop's index then fills the 16 bits the
+    batched item codes give it). Sampled loops (the first, the last and others) of both against
+    the oracle's step to 1e-12; the batch against loop_step to 1e-12 on every loop (loop_step
+    packs rows of neighbouring loops into one transform, the batch rows of one loop, so they
+    agree to rounding); the persistent schedule equal to the per-pass one bit for bit."""
+    n, Nx, Ns, L, dtau = 65535, 8, 8, 5.0, 1e-3
+    rng = np.random.default_rng(65535)
+    band = K.band_mask(Nx, Ns)
+    u = (rng.standard_normal((n, Ns, Nx // 2 + 1)) + 1j * rng.standard_normal((n, Ns, Nx // 2 + 1))) * 0.3 * band
+    T = rng.uniform(10.0, 30.0, n)
+    ud = torch.from_numpy(u).to(DEV)
+    Td = torch.from_numpy(T).to(DEV)
+    api.loop_step(ud, Td, L, dtau, api.IMEX, 1)
+    torch.cuda.synchronize()
+    uo, To = ud.cpu().numpy(), Td.cpu().numpy()
+    b = api.Batch([(L, Nx, Ns)] * n)
+    assert b.offsets[-1] == (n - 1) * Ns * (Nx // 2 + 1)  # one shape: the pool is the loops back to back
+    out = {}
+    for schedule in (api.Batch.PER_PASS, api.Batch.PERSISTENT):
+        b.set_schedule(schedule)
+        pool = torch.from_numpy(u.reshape(-1).copy()).to(DEV)
+        Tb = torch.from_numpy(T.copy()).to(DEV)
+        b.step(pool, Tb, dtau, api.IMEX, 1)
+        torch.cuda.synchronize()
+        assert b.status() == 0
+        out[schedule] = (pool.cpu().numpy().reshape(u.shape), Tb.cpu().numpy())
+    ub, Tbatch = out[api.Batch.PER_PASS]
+    assert np.array_equal(out[api.Batch.PERSISTENT][0], ub) and np.array_equal(out[api.Batch.PERSISTENT][1], Tbatch)
+    w = np.full(Nx // 2 + 1, 2.0)
+    w[0] = 1.0
+    diff = np.sqrt(np.sum(w * np.abs(ub - uo) ** 2, axis=(1, 2)) / np.sum(w * np.abs(uo) ** 2, axis=(1, 2)))
+    assert diff.max() < TOL, (int(diff.argmax()), diff.max())
+    assert np.all(np.abs(Tbatch - To) <= TOL * To)
+    for i in [0, 1, 2, 255, 256, 32767, n - 3, n - 2, n - 1] + list(rng.integers(0, n, 16)):
+        ue, Te, _ = K.step(u[i], T[i], L, dtau, api.IMEX, 1)
+        for got, Tg in ((uo[i], To[i]), (ub[i], Tbatch[i])):
+            assert wrel(got, ue) < TOL, (i, wrel(got, ue))
+            assert abs(Tg - Te) <= TOL * Te, i
