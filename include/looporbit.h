@@ -273,7 +273,8 @@ int loop_update(double L, int Nx, int Ns, int nloops, double* T, double* uhat,
  * The step is the one loop_step takes (Sec. 4.2), applied to every loop of the batch.
  *
  * loop_batch_create builds a plan on the current device. This host call allocates the
- * plan's device tables, so it must run outside stream capture. Each loop needs a power-of-
+ * plan's device tables and runs a small probe kernel on the null stream (it finds the XCDs the
+ * persistent schedule uses) and waits for it, so it must run outside stream capture. Each loop needs a power-of-
  * two Nx in [8, 512] and Ns in [8, 1024]. The loops' spectra live back to back in one
  * rfft-layout pool, in the order given, at the offsets loop_batch_info reports (in complex
  * values). Periods T[nloops]; J_hist, if not NULL, is [nsteps][nloops].
