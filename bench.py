@@ -258,34 +258,44 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(b) / kc
 
+    def captured(step_call):
+        """the call recorded once into a HIP graph (after one call off the graph)"""
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step_call(2)
+        stream.wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step_call(kc)
+        g.replay()
+        return g
+
     tuned = batch.config()["schedule"]
     batch.set_schedule(api.Batch.PERSISTENT)
     pool, T = pool0.clone(), T0.clone()
     batch.step(pool, T, dtau, scheme, 2)
     persistent_ms = gpu_ms_per_step(lambda: batch.step(pool, T, dtau, scheme, kc))
     assert batch.status() == 0
+    pool, T = pool0.clone(), T0.clone()
+    persistent_graph = captured(lambda n: batch.step(pool, T, dtau, scheme, n))
+    persistent_graph_ms = gpu_ms_per_step(persistent_graph.replay)
+    assert batch.status() == 0 and bool(torch.isfinite(T).all())
     if tuned.startswith("streams"):
         batch.set_schedule(api.Batch.STREAMS, int(tuned.split("-")[1]))
     else:
         batch.set_schedule(api.Batch.PER_PASS)
     pool, T = pool0.clone(), T0.clone()
-    side = torch.cuda.Stream()
-    side.wait_stream(stream)
-    with torch.cuda.stream(side):
-        batch.step(pool, T, dtau, scheme, 2)  # first call off the graph
-    stream.wait_stream(side)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        batch.step(pool, T, dtau, scheme, kc)
-    graph.replay()
+    graph = captured(lambda n: batch.step(pool, T, dtau, scheme, n))
     graph_ms = gpu_ms_per_step(graph.replay)
     assert batch.status() == 0 and bool(torch.isfinite(T).all())
     schedules = {"tuned": tuned, "steps": kc, "tuned_eager_ms_per_step": round(e0.elapsed_time(e1) / steps, 5),
                  "persistent_ms_per_step": round(persistent_ms, 5),
+                 "persistent_graph_replay_ms_per_step": round(persistent_graph_ms, 5),
                  "tuned_graph_replay_ms_per_step": round(graph_ms, 5),
-                 "method": "persistent: loop_batch_step with LOOP_BATCH_PERSISTENT, one launch for all steps; "
-                           "graph: the tuned schedule's loop_batch_step call of all steps recorded into a "
-                           "HIP graph (torch.cuda.CUDAGraph) and replayed"}
+                 "method": "persistent: loop_batch_step with LOOP_BATCH_PERSISTENT, one launch for all steps, "
+                           "eager and recorded into a HIP graph (torch.cuda.CUDAGraph) and replayed; graph: the "
+                           "tuned schedule's loop_batch_step call of all steps recorded and replayed"}
 
     # ---- plain method on the same loops: loop_step per loop, one after another
     plain = None
