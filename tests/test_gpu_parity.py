@@ -135,6 +135,27 @@ def test_full_size_large_batch_sampled(api):
     assert np.all(np.isfinite(G)) and np.all(J > 0)
 
 
+def test_full_size_translation_equivariance(api):
+    """All 64 loops of 256 x 1024 (L = 100): the flow of a loop shifted in x by d and in s by
+    sigma is the shifted flow, and J and dJ/dT do not change. A shift is a phase rotation
+    exp(-i (q_j d + omega_k sigma)) of the spectrum, exact for band-limited fields, so any pass
+    that mixed up an index, a sign or a conjugate half at full size would show here."""
+    specs = loopgen.config_loops(5)
+    u = np.stack([s.uhat for s in specs])
+    T = np.array([s.T for s in specs])
+    L = specs[0].L
+    q, om = K.wavenumbers(L, 256, 1024)
+    phase = np.exp(-1j * (q * (0.37 * L) + om * 0.19))
+    ud, Td = to_dev(u, T)
+    G, dJdT, J = (x.cpu().numpy() for x in api.loop_adjoint_grad(ud, Td, L))
+    us, Ts = to_dev(u * phase, T)
+    Gs, dJdTs, Js = (x.cpu().numpy() for x in api.loop_adjoint_grad(us, Ts, L))
+    for i in range(len(specs)):
+        assert relerr(Gs[i], G[i] * phase, 256) < TOL, (i, relerr(Gs[i], G[i] * phase, 256))
+        assert abs(Js[i] - J[i]) <= TOL * J[i], i
+        assert abs(dJdTs[i] - dJdT[i]) <= TOL * dT_scale(u[i], T[i], L), i
+
+
 def test_batch_is_bitwise_equal_to_single_loops(api):
     Nx, Ns, L = 64, 128, 22.0
     u, T = make_batch(Nx, Ns, L, 5, seed=99)
