@@ -110,6 +110,27 @@ def step_flops(Nx, Ns):
     return 20 * C * Ns * lg(Ns) + 15 * Ns * Nx * lg(Nx) + 55 * S + 4 * Nx * Ns
 
 
+def copy_ceiling_gbs(device, mib=512, reps=20):
+    """Read plus write bandwidth of a plain device-to-device copy of `mib` MiB (larger than the
+    256 MB Infinity Cache), timed between events over `reps` back-to-back copies: the practical
+    streaming ceiling the kernels' HBM figures can be set against. Outside any timed region."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.empty(n, dtype=torch.float64, device=device).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * 8 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbs
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch from the committed counter summary, if it was taken on this source."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
@@ -243,6 +264,9 @@ def main():
                 # the whole step, every pass, as the timed region ran it (its kernels may overlap)
                 "step_achieved": round(step_bytes / (e0.elapsed_time(e1) * 1e-3 / steps) / 1e9, 1),
                 "step_frac": round(step_bytes / (e0.elapsed_time(e1) * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS, 4)}
+    copy_gbs = copy_ceiling_gbs(dev)
+    roofline["copy_gbs"] = round(copy_gbs, 1)  # plain 512 MiB device copy, same machine
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
 
     # ---- context for the schedule choice (same loops, min(K, 500) steps each, not the headline):
     # all steps in one persistent launch, and the tuned schedule's steps recorded once into a
@@ -584,6 +608,10 @@ def bench_autograd(args, cfg, specs, steps, dtau, scheme):
                 "step_achieved": round(step_bytes / (gpu_s / steps) / 1e9, 1),
                 "step_frac": round(step_bytes / (gpu_s / steps) / 1e9 / HBM_PEAK_GBS, 4),
                 "traced_kernels_sum_vs_step": round(traced_step_us / (gpu_s / steps * 1e6), 3)}
+    copy_gbs = copy_ceiling_gbs(dev)
+    roofline["copy_gbs"] = round(copy_gbs, 1)  # plain 512 MiB device copy, same machine
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    roofline["step_frac_of_copy"] = round(step_bytes / (gpu_s / steps) / 1e9 / copy_gbs, 4)
 
     # ---- the same path on rfft-layout tensors
     k_r = min(steps, 200)
